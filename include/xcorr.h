@@ -1,0 +1,148 @@
+/*
+ * xcorr.h -- C ABI of the MI355X (gfx950) X-engine.
+ *
+ * The X-engine of an FX correlator receives channelised voltages and, per
+ * frequency channel, forms the conjugate multiply-accumulate (CMAC) of every
+ * input pair over an integration (paper: Section 2.4 "X-engine"; Eq. 2 of
+ * Section 3.2 defines a visibility as the time average of S1* . S2).  This
+ * library computes, for each channel f and each pair j <= i of the N inputs,
+ *
+ *     V_ij[f] = sum_t x_i[f,t] * conj(x_j[f,t])            (exact, int32)
+ *
+ * accumulated across ingest calls until a dump.  Pair (i, j) is stored at
+ * p = i(i+1)/2 + j; autos are included, so P = N(N+1)/2 pairs per channel.
+ *
+ * Input formats (Section 2.1 "F-engine": 4-bit real + 4-bit imaginary after
+ * requantisation; Section 2.4: the fluff step widens them to 8+8 bits):
+ *   sample_bits = 4 : uint8 per sample, high nibble = real, low nibble =
+ *                     imaginary, two's complement in [-8, 7].
+ *   sample_bits = 8 : int8 real then int8 imaginary, each in [-127, 127]
+ *                     (-128 is outside the contract: its negation does not fit).
+ * Input layout XCORR_LAYOUT_TFN: time-major [T][F][N] samples, i.e. sample
+ * (t, f, i) at element ((t*F + f)*N + i).
+ *
+ * Output of a dump: [F][P][2] (re, im) int32 for the integer paths, float32
+ * for the FP16 path.  Its size is Eq. 1 of Section 2.2 with 4-byte values:
+ * N(N+1)/2 * F * 2 * 4 bytes.
+ *
+ * Conventions.  Every call returns XCORR_OK (0) or a negative XCORR_E_* code;
+ * no exception crosses the ABI.  Pointers named d_* are device pointers on
+ * the current HIP device; the caller owns all device memory (the library
+ * allocates none).  `stream` is a hipStream_t (NULL = the null stream); work
+ * is enqueued asynchronously and the host does not synchronise.  A context is
+ * not thread-safe; distinct contexts are independent.  Calls that overlap on
+ * one context's workspace from different streams race.
+ */
+#ifndef XCORR_H
+#define XCORR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define XCORR_OK 0
+#define XCORR_E_INVAL (-1)    /* bad argument, shape, format or path */
+#define XCORR_E_NOMEM (-2)    /* workspace too small / admission budget exceeded */
+#define XCORR_E_OVERFLOW (-3) /* the integration would pass the int32 bound */
+#define XCORR_E_HIP (-4)      /* a HIP runtime call failed (see xcorr_last_error) */
+#define XCORR_E_DEVICE (-5)   /* the current device is not a gfx950 GPU */
+
+/* compute paths */
+#define XCORR_PATH_PLAIN 0    /* VALU int32 multiply-adds, no matrix cores */
+#define XCORR_PATH_I8_MFMA 1  /* int8 MFMA, int32 accumulation (exact) */
+#define XCORR_PATH_F16_MFMA 2 /* 8-bit input only: FP16 MFMA, FP32 accumulation */
+
+/* input layouts */
+#define XCORR_LAYOUT_TFN 0
+
+/* samples the int32 accumulators can take before any entry may overflow:
+ * 4-bit: |contribution| <= 128 per sample (autos at -8-8i), floor((2^31-1)/128);
+ * 8-bit: |contribution| <= 2*127^2 per sample, floor((2^31-1)/32258). */
+#define XCORR_TMAX_4BIT 16777215LL
+#define XCORR_TMAX_8BIT 66572LL
+
+typedef struct xcorr_ctx xcorr_ctx;
+typedef struct xcorr_batch xcorr_batch;
+
+typedef struct {
+    int32_t n_inputs;     /* N >= 1 (input k = 2*feed + polarisation) */
+    int32_t n_chans;      /* F >= 1 */
+    int32_t sample_bits;  /* 4 or 8 */
+    int32_t path;         /* XCORR_PATH_* */
+    int32_t layout;       /* XCORR_LAYOUT_TFN */
+    int32_t tile;         /* MFMA paths: diagonal block size in 32-input blocks
+                             (2, 3, 4 or 6); 0 = tuned value from the tune
+                             cache, else a built-in choice */
+    int64_t max_samples_per_dump; /* 0 = the format's T_max; larger than
+                                     T_max is XCORR_E_OVERFLOW */
+} xcorr_config;
+
+typedef struct {
+    int64_t samples_integrated; /* since the last dump */
+    int64_t samples_total;      /* since init */
+    int64_t ingests;
+    int64_t dumps;
+    int64_t kernel_launches;
+    uint64_t seq_gaps;          /* missing sequence numbers since the last dump */
+    uint64_t seq_gaps_total;
+    int32_t tile;               /* diagonal block size in use (MFMA paths) */
+    int32_t regions_per_chan;   /* work-groups per channel in one ingest */
+} xcorr_stats_t;
+
+/*
+ * Sizes for admission by memory (pure host, no device call).
+ *   workspace_bytes : device bytes a context needs (the accumulators,
+ *                     F*P*2*4 bytes, rounded up to 256)
+ *   out_bytes       : bytes one dump writes (Eq. 1 of Section 2.2, 4-byte values)
+ *   t_max           : largest integration, in samples, that stays exact
+ * Any output pointer may be NULL.  Errors: XCORR_E_INVAL for an invalid
+ * config (N < 1, F < 1, bits not 4/8, unknown path or layout, FP16 path with
+ * 4-bit input, tile not in {0,2,3,4,6}); XCORR_E_OVERFLOW if
+ * max_samples_per_dump > t_max.
+ */
+int xcorr_query(const xcorr_config *cfg, size_t *workspace_bytes, size_t *out_bytes, int64_t *t_max);
+
+/*
+ * Create a context on the current HIP device.  d_workspace (>= workspace_bytes
+ * from xcorr_query) is borrowed until xcorr_destroy; its contents need no
+ * initialisation.  Errors: as xcorr_query, XCORR_E_NOMEM if ws_bytes is too
+ * small or d_workspace is NULL, XCORR_E_DEVICE if the device is not gfx950,
+ * XCORR_E_HIP on a runtime failure.  *out is set only on success.
+ */
+int xcorr_init(const xcorr_config *cfg, void *d_workspace, size_t ws_bytes, xcorr_ctx **out);
+
+/*
+ * Correlate n_samples >= 1 time samples, d_volts = [n_samples][F][N] in the
+ * configured format, and add them to the integration (the first ingest after
+ * a dump overwrites the accumulators).  d_volts stays caller-owned and must
+ * stay valid until the stream passes this call.  Any n_samples is allowed:
+ * partial tiles are zero-padded, which is exact.  `seq` is the caller's block
+ * sequence number; gaps (seq != previous seq + 1) are counted, not fatal.
+ * Errors (checked before anything is enqueued): XCORR_E_INVAL (NULL ctx or
+ * pointer, n_samples < 1), XCORR_E_OVERFLOW if samples_integrated + n_samples
+ * would exceed max_samples_per_dump, XCORR_E_HIP if a launch fails.
+ */
+int xcorr_ingest(xcorr_ctx *ctx, const void *d_volts, int64_t n_samples, uint64_t seq, void *stream);
+
+/*
+ * Write the integration to d_out ([F][P][2], out_bytes from xcorr_query) and
+ * start a new one.  A dump of an empty integration writes zeros.
+ * n_integrated / n_gaps (may be NULL) receive the samples and the counted
+ * sequence gaps of the integration just closed.
+ */
+int xcorr_dump(xcorr_ctx *ctx, void *d_out, int64_t *n_integrated, uint64_t *n_gaps, void *stream);
+
+int xcorr_stats(const xcorr_ctx *ctx, xcorr_stats_t *out);
+int xcorr_destroy(xcorr_ctx *ctx);
+const char *xcorr_strerror(int code);
+/* Detail of the last XCORR_E_HIP / XCORR_E_DEVICE on this thread. */
+const char *xcorr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* XCORR_H */

@@ -1,0 +1,35 @@
+// Internal declarations shared by the host API and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace xc {
+
+// Work split of one channel's lower triangle for the MFMA paths.  Inputs are
+// grouped into 32-input blocks (NB = ceil(N/32)); the block triangle is cut
+// into diagonal segments of D blocks (triangular regions) and the rectangles
+// between segments (rectangular regions, only when D <= 4).  One work-group
+// handles one (channel, region).
+struct Plan {
+    int D = 0;              // diagonal segment size in blocks
+    int NB = 0;             // 32-input blocks
+    int nseg = 0;           // diagonal segments
+    int regions = 0;        // regions per channel
+};
+
+Plan make_plan(int N, int D);
+bool plan_supported(int N, int D);
+
+// Launchers: enqueue on `stream`, return hipSuccess or the launch error.
+// `accumulate` = 0 overwrites the accumulators, 1 adds to them.
+// T <= kMaxSamplesPerLaunch for the MFMA paths (the host splits longer ingests).
+constexpr int64_t kMaxSamplesPerLaunch4 = 131071;  // |16re*16re| <= 2^14 per sample
+constexpr int64_t kMaxSamplesPerLaunch8 = 133143;  // |re*re| <= 127^2 per sample
+
+hipError_t launch_plain(int bits, const uint8_t *volts, int64_t T, int F, int N, int2 *acc,
+                        int accumulate, hipStream_t s);
+hipError_t launch_mfma4(const Plan &pl, int kc, const uint8_t *volts, int64_t T, int F, int N,
+                        int2 *acc, int accumulate, hipStream_t s);
+hipError_t launch_dump(const void *acc, void *out, int64_t bytes, int empty, hipStream_t s);
+
+}  // namespace xc

@@ -1,0 +1,516 @@
+// gfx950 kernels of the X-engine cross-multiply-accumulate.
+//
+// For every channel f and pair j <= i:  V_ij = sum_t x_i[t] * conj(x_j[t])
+// (paper Section 2.4 "X-engine"; Eq. 2 of Section 3.2), i.e. per channel the
+// lower triangle of the Hermitian rank-T update X X^H, accumulated in int32.
+//
+//   xc_plain_kernel   VALU int32 multiply-adds (the comparison path)
+//   xc_mfma4_kernel   4+4-bit input, int8 MFMA v_mfma_i32_32x32x32_i8
+//   xc_dump_kernel    accumulator -> caller buffer copy (or zero fill)
+#include "xcorr_internal.h"
+
+#include <algorithm>
+
+namespace xc {
+namespace {
+
+typedef int v2i __attribute__((ext_vector_type(2)));
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+typedef __attribute__((address_space(3))) v2i lds_v2i;
+
+constexpr int kThreads = 256;
+
+// Work-group b is dispatched to XCD b % 8.  Give each XCD a contiguous range
+// of work items so that the regions of one channel, and neighbouring channels
+// (adjacent bytes of every time row), share that XCD's L2.  The grid is a
+// multiple of 8; callers drop items >= the real count.
+__device__ __forceinline__ int xcd_item()
+{
+    const int per = gridDim.x >> 3;
+    return (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+}
+
+inline int xcd_grid(int nitems) { return ((nitems + 7) / 8) * 8; }
+
+// 16 consecutive bytes of one (t, f) row starting at input i0; zero outside
+// [0,T) x [0,N).  bps = bytes per sample.  vec_ok: rows are 16-byte aligned
+// and N*bps is a multiple of 16, so a piece is either fully inside or fully
+// outside the row.
+__device__ __forceinline__ v4i load_piece(const uint8_t *__restrict__ volts, int64_t t, int64_t T,
+                                          int f, int F, int N, int i0, int bps, int vec_ok)
+{
+    v4i r = {0, 0, 0, 0};
+    if (t >= T || i0 >= N)
+        return r;
+    const int64_t row_bytes = (int64_t)N * bps;
+    const uint8_t *src = volts + (t * F + f) * row_bytes + (int64_t)i0 * bps;
+    if (vec_ok)
+        return *reinterpret_cast<const v4i *>(src);
+    const int avail = (int)std::min<int64_t>(16, row_bytes - (int64_t)i0 * bps);
+    uint32_t w[4] = {0, 0, 0, 0};
+    for (int b = 0; b < 16; ++b)
+        if (b < avail)
+            w[b >> 2] |= (uint32_t)src[b] << (8 * (b & 3));
+    r.x = (int)w[0];
+    r.y = (int)w[1];
+    r.z = (int)w[2];
+    r.w = (int)w[3];
+    return r;
+}
+
+__device__ __forceinline__ int sext_nibble(uint32_t x, int lsb)
+{
+    return (int)(x << (28 - lsb)) >> 28;
+}
+
+// ---------------------------------------------------------------------------
+// Plain path: one work-group per (channel, 64x64 pair tile of the lower
+// triangle).  Thread (tx, ty) owns inputs i = 4ty..4ty+3 and j = 4tx..4tx+3 of
+// the tile: 16 pairs, re and im in int32 registers.  Time is staged through
+// LDS in chunks of 32 samples as raw packed bytes.
+template <int BITS, int VEC>
+__global__ __launch_bounds__(kThreads) void xc_plain_kernel(
+    const uint8_t *__restrict__ volts, int64_t T, int F, int N, int ntiles, int nitems,
+    int2 *__restrict__ acc, int accumulate)
+{
+    constexpr int BPS = BITS == 4 ? 1 : 2;
+    constexpr int KC = 32;
+    constexpr int SEG = 64 * BPS;               // bytes of 64 inputs in one time row
+    constexpr int PIECES = 2 * KC * SEG / 16;   // 16-byte pieces per chunk (rows + cols)
+    __shared__ __attribute__((aligned(16))) uint8_t sm[2][KC][SEG];
+
+    const int item = xcd_item();
+    if (item >= nitems)
+        return;
+    const int f = item / ntiles;
+    const int tile = item - f * ntiles;
+    int I = (int)((sqrtf(8.f * tile + 1.f) - 1.f) * 0.5f);
+    while ((I + 1) * (I + 2) / 2 <= tile)
+        ++I;
+    while (I * (I + 1) / 2 > tile)
+        --I;
+    const int J = tile - I * (I + 1) / 2;
+
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    int ar[4][4], ai[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            ar[a][b] = ai[a][b] = 0;
+
+    for (int64_t t0 = 0; t0 < T; t0 += KC) {
+#pragma unroll
+        for (int k = 0; k < PIECES / kThreads; ++k) {
+            const int pc = tid + kThreads * k;
+            const int seg = pc / (KC * SEG / 16);
+            const int rem = pc - seg * (KC * SEG / 16);
+            const int t = rem / (SEG / 16);
+            const int p = rem - t * (SEG / 16);
+            const int i0 = (seg ? J : I) * 64 + p * 16 / BPS;
+            *reinterpret_cast<v4i *>(&sm[seg][t][p * 16]) =
+                load_piece(volts, t0 + t, T, f, F, N, i0, BPS, VEC);
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int t = 0; t < KC; ++t) {
+            int xr[4], xi[4], yr[4], yi[4];
+            if constexpr (BITS == 4) {
+                const uint32_t a = *reinterpret_cast<const uint32_t *>(&sm[0][t][ty * 4]);
+                const uint32_t b = *reinterpret_cast<const uint32_t *>(&sm[1][t][tx * 4]);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    xr[k] = sext_nibble(a, 8 * k + 4);
+                    xi[k] = sext_nibble(a, 8 * k);
+                    yr[k] = sext_nibble(b, 8 * k + 4);
+                    yi[k] = sext_nibble(b, 8 * k);
+                }
+            } else {
+                const int8_t *a = reinterpret_cast<const int8_t *>(&sm[0][t][ty * 8]);
+                const int8_t *b = reinterpret_cast<const int8_t *>(&sm[1][t][tx * 8]);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    xr[k] = a[2 * k];
+                    xi[k] = a[2 * k + 1];
+                    yr[k] = b[2 * k];
+                    yi[k] = b[2 * k + 1];
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    ar[a][b] += xr[a] * yr[b] + xi[a] * yi[b];
+                    ai[a][b] += xi[a] * yr[b] - xr[a] * yi[b];
+                }
+        }
+        __syncthreads();
+    }
+
+    const int64_t P = (int64_t)N * (N + 1) / 2;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const int i = I * 64 + ty * 4 + a;
+        if (i >= N)
+            continue;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int j = J * 64 + tx * 4 + b;
+            if (j > i)
+                continue;
+            int2 *dst = acc + (int64_t)f * P + (int64_t)i * (i + 1) / 2 + j;
+            int re = ar[a][b], im = ai[a][b];
+            if (accumulate) {
+                const int2 o = *dst;
+                re += o.x;
+                im += o.y;
+            }
+            *dst = make_int2(re, im);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 4+4-bit int8-MFMA path.
+//
+// Per channel the packed voltages form a matrix X[i][t] (one byte per sample).
+// With R = 16*re and Im16 = 16*im as int8 (a nibble moved to the high half of
+// a byte is 16x its value, exact), the four real products
+//     RR = R R^T, II = Im16 Im16^T, IR = Im16 R^T, RI = R Im16^T
+// give 256*Re V = RR + II and 256*Im V = IR - RI on every 32x32 tile.  Each
+// of the four waves of a work-group computes one of the four products for
+// every tile of its region, so the waves carry identical MFMA counts for any
+// region shape.  Raw packed bytes are staged in LDS in their HBM order
+// [t][inputs]; ds_read_b64_tr_b8 turns 8 time rows x 16 inputs into the
+// per-lane [input][8 samples] MFMA operand layout, and two masks unpack it.
+//
+// v_mfma_i32_32x32x32_i8 operand layout (gfx950): lane l supplies row l%32,
+// k-half l/32, 16 int8; result register r of lane l is row 8(r/4) + 4(l/32) +
+// r%4, column l%32.
+
+__device__ __forceinline__ v4i frag_tr8(const uint8_t *p, int eight_rows)
+{
+    const v2i lo = __builtin_amdgcn_ds_read_tr8_b64_v2i32((lds_v2i *)p);
+    const v2i hi = __builtin_amdgcn_ds_read_tr8_b64_v2i32((lds_v2i *)(p + eight_rows));
+    return v4i{lo.x, lo.y, hi.x, hi.y};
+}
+
+// A nibble moved into the high half of a byte reads as 16x its value: the
+// real part is x & 0xF0 (shift 0), the imaginary part (x << 4) & 0xF0.
+__device__ __forceinline__ v4i nib16(v4i x, int shift) { return (x << shift) & (int)0xF0F0F0F0; }
+
+__device__ __forceinline__ v16i mfma_i8(v4i a, v4i b, v16i c)
+{
+    return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
+}
+
+// Wave roles: which real product a wave accumulates, and the nibble shifts of
+// its A (row) and B (column) operands.
+enum Role { kRR = 0, kII = 1, kIR = 2, kRI = 3 };
+__device__ __forceinline__ int role_shift_a(int role) { return (role == kII || role == kIR) ? 4 : 0; }
+__device__ __forceinline__ int role_shift_b(int role) { return (role == kII || role == kRI) ? 4 : 0; }
+
+// One 32-sample K step over a region.  TRI: d x d blocks from LDS column 0,
+// tiles (I, J <= I).  RECT: D row blocks from LDS column 0 by D column blocks
+// from LDS column 32*D, all D*D tiles.  Tile t of the accumulator array is
+// (I, J) in row-major order of the region's active tiles.
+template <int D, bool TRI>
+__device__ __forceinline__ void k_step(const uint8_t *base, int S, int sa, int sb, v16i *acc)
+{
+    if constexpr (TRI) {
+        // row by row: only the column operands of rows <= I stay live
+        v4i B[D];
+        int t = 0;
+#pragma unroll
+        for (int I = 0; I < D; ++I) {
+            const v4i x = frag_tr8(base + 32 * I, 8 * S);
+            const v4i A = nib16(x, sa);
+            B[I] = nib16(x, sb);
+#pragma unroll
+            for (int J = 0; J <= I; ++J, ++t)
+                acc[t] = mfma_i8(A, B[J], acc[t]);
+        }
+    } else {
+        v4i A[D], B[D];
+#pragma unroll
+        for (int I = 0; I < D; ++I)
+            A[I] = nib16(frag_tr8(base + 32 * I, 8 * S), sa);
+#pragma unroll
+        for (int J = 0; J < D; ++J)
+            B[J] = nib16(frag_tr8(base + 32 * D + 32 * J, 8 * S), sb);
+        int t = 0;
+#pragma unroll
+        for (int I = 0; I < D; ++I)
+#pragma unroll
+            for (int J = 0; J < D; ++J, ++t)
+                acc[t] = mfma_i8(A[I], B[J], acc[t]);
+    }
+}
+
+constexpr int tri_I(int t)
+{
+    int I = 0;
+    while ((I + 1) * (I + 2) / 2 <= t)
+        ++I;
+    return I;
+}
+constexpr int tri_J(int t) { return t - tri_I(t) * (tri_I(t) + 1) / 2; }
+
+constexpr int mfma4_lds_row(int D) { return 32 * D * (D <= 4 ? 2 : 1) + 16; }
+
+// Whole work-group body for one region shape.  row_blk / col_blk: first
+// 32-input block of the region's rows / columns.
+template <int D, bool TRI, int KC, int VEC>
+__device__ __forceinline__ void mfma4_region(uint8_t *smem, const uint8_t *__restrict__ volts,
+                                             int64_t T, int F, int N, int f, int row_blk, int col_blk,
+                                             int2 *__restrict__ acc_out, int accumulate)
+{
+    constexpr int S = mfma4_lds_row(D);                 // LDS bytes per time row (+16 pad)
+    constexpr int NT = TRI ? D * (D + 1) / 2 : D * D;   // accumulator tiles per wave
+    constexpr int BUF = KC * S;
+    constexpr int G = 4;                                // tiles per epilogue round
+    constexpr int NP = (TRI ? 2 : 4) * D;               // 16-byte fill pieces per time row
+    constexpr int PMAX = (KC * NP + kThreads - 1) / kThreads;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int g = lane >> 4, q = lane & 15;
+    const int frag_off = ((g >> 1) * 16 + (q >> 1)) * S + (g & 1) * 16 + (q & 1) * 8;
+    const int sa = role_shift_a(wave), sb = role_shift_b(wave);
+
+    // fixed assignment of 16-byte fill pieces to threads
+    int p_t[PMAX], p_i0[PMAX], p_lds[PMAX];
+#pragma unroll
+    for (int k = 0; k < PMAX; ++k) {
+        const int pc = tid + kThreads * k;
+        const int t = pc / NP, p = pc - t * NP;
+        p_t[k] = pc < KC * NP ? t : -1;
+        p_i0[k] = p < 2 * D ? row_blk * 32 + p * 16 : col_blk * 32 + (p - 2 * D) * 16;
+        p_lds[k] = t * S + p * 16;
+    }
+
+    v16i acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+        acc[t] = v16i{};
+
+    const int64_t nchunks = (T + KC - 1) / KC;
+    v4i pre[PMAX];
+    auto load_chunk = [&](int64_t c) {
+#pragma unroll
+        for (int k = 0; k < PMAX; ++k)
+            pre[k] = p_t[k] >= 0 ? load_piece(volts, c * KC + p_t[k], T, f, F, N, p_i0[k], 1, VEC)
+                                 : v4i{0, 0, 0, 0};
+    };
+    auto store_chunk = [&](int64_t c) {
+        uint8_t *buf = smem + (c & 1) * BUF;
+#pragma unroll
+        for (int k = 0; k < PMAX; ++k)
+            if (p_t[k] >= 0)
+                *reinterpret_cast<v4i *>(buf + p_lds[k]) = pre[k];
+    };
+
+    if (nchunks > 0) {
+        load_chunk(0);
+        store_chunk(0);
+    }
+    __syncthreads();
+    for (int64_t c = 0; c < nchunks; ++c) {
+        if (c + 1 < nchunks)
+            load_chunk(c + 1);
+        const uint8_t *buf = smem + (c & 1) * BUF + frag_off;
+#pragma unroll
+        for (int ks = 0; ks < KC / 32; ++ks)
+            k_step<D, TRI>(buf + ks * 32 * S, S, sa, sb, acc);
+        if (c + 1 < nchunks)
+            store_chunk(c + 1);
+        __syncthreads();
+    }
+
+    // Epilogue: the four waves' products meet in LDS, G tiles per round.
+    // 256*Re = RR + II and 256*Im = IR - RI; each product is a multiple of 256.
+    int *stage = reinterpret_cast<int *>(smem);
+    const int64_t P = (int64_t)N * (N + 1) / 2;
+    int2 *out_f = acc_out + (int64_t)f * P;
+#pragma unroll
+    for (int t0 = 0; t0 < NT; t0 += G) {
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            if (t0 + u < NT) {
+#pragma unroll
+                for (int rg = 0; rg < 16; ++rg) {
+                    const int row = 8 * (rg >> 2) + 4 * (lane >> 5) + (rg & 3);
+                    stage[((wave * G + u) << 10) + row * 32 + (lane & 31)] = acc[t0 + u][rg];
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const int t = t0 + u;
+            if (t < NT) {
+                const int I = TRI ? tri_I(t) : t / D;
+                const int J = TRI ? tri_J(t) : t % D;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int e = tid + kThreads * k;
+                    const int i = (row_blk + I) * 32 + (e >> 5);
+                    const int j = (col_blk + J) * 32 + (e & 31);
+                    if (i < N && j <= i) {
+                        const int rr = stage[((0 * G + u) << 10) + e];
+                        const int ii = stage[((1 * G + u) << 10) + e];
+                        const int ir = stage[((2 * G + u) << 10) + e];
+                        const int ri = stage[((3 * G + u) << 10) + e];
+                        int re = (rr >> 8) + (ii >> 8);
+                        int im = (ir >> 8) - (ri >> 8);
+                        int2 *dst = out_f + (int64_t)i * (i + 1) / 2 + j;
+                        if (accumulate) {
+                            const int2 o = *dst;
+                            re += o.x;
+                            im += o.y;
+                        }
+                        *dst = make_int2(re, im);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// One work-group per (channel, region).  Regions of one channel: nseg
+// triangles on the diagonal segments, then the nseg(nseg-1)/2 rectangles
+// (a, b), a > b, in row-major order.  Segments are D blocks each (the input
+// count is zero-padded up to 32*D*nseg).
+template <int D, int KC, int VEC>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void xc_mfma4_kernel(const uint8_t *__restrict__ volts, int64_t T, int F, int N, int nseg, int R,
+                     int nitems, int2 *__restrict__ acc_out, int accumulate)
+{
+    constexpr int S = mfma4_lds_row(D);
+    constexpr int STAGE = 4 * 4 * 1024 * 4;
+    constexpr int SMEM = 2 * KC * S > STAGE ? 2 * KC * S : STAGE;
+    __shared__ __attribute__((aligned(16))) uint8_t smem[SMEM];
+
+    const int item = xcd_item();
+    if (item >= nitems)
+        return;
+    const int f = item / R;
+    const int r = item - f * R;
+    if (r < nseg) {
+        mfma4_region<D, true, KC, VEC>(smem, volts, T, F, N, f, r * D, r * D, acc_out, accumulate);
+    } else if constexpr (D <= 4) {
+        const int k = r - nseg;
+        int a = (int)((1.f + sqrtf(1.f + 8.f * k)) * 0.5f);
+        while (a * (a - 1) / 2 > k)
+            --a;
+        while ((a + 1) * a / 2 <= k)
+            ++a;
+        const int b = k - a * (a - 1) / 2;
+        mfma4_region<D, false, KC, VEC>(smem, volts, T, F, N, f, a * D, b * D, acc_out, accumulate);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Dump: copy the accumulators to the caller's buffer (16-byte vectors plus an
+// 8-byte tail), or fill it with zeros for an empty integration.
+__global__ __launch_bounds__(kThreads) void xc_dump_kernel(const int2 *__restrict__ src,
+                                                           int2 *__restrict__ dst, int64_t n8,
+                                                           int empty)
+{
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    const int64_t n16 = n8 >> 1;
+    const v4i *s16 = reinterpret_cast<const v4i *>(src);
+    v4i *d16 = reinterpret_cast<v4i *>(dst);
+    for (int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x; k < n16; k += stride)
+        d16[k] = empty ? v4i{0, 0, 0, 0} : s16[k];
+    if ((n8 & 1) && blockIdx.x == 0 && threadIdx.x == 0)
+        dst[n8 - 1] = empty ? make_int2(0, 0) : src[n8 - 1];
+}
+
+}  // namespace
+
+Plan make_plan(int N, int D)
+{
+    Plan p;
+    p.D = D;
+    p.NB = (N + 31) / 32;
+    p.nseg = (p.NB + D - 1) / D;
+    p.regions = p.nseg + p.nseg * (p.nseg - 1) / 2;
+    return p;
+}
+
+bool plan_supported(int N, int D)
+{
+    const int nb = (N + 31) / 32;
+    if (D < 1 || D > 6)
+        return false;
+    // D <= 4 kernels also have rectangular regions; D = 5, 6 are one triangle
+    return D <= 4 ? (D > 1 || nb == 1) : nb <= D;
+}
+
+hipError_t launch_plain(int bits, const uint8_t *volts, int64_t T, int F, int N, int2 *acc,
+                        int accumulate, hipStream_t s)
+{
+    const int nb = (N + 63) / 64;
+    const int ntiles = nb * (nb + 1) / 2;
+    const int64_t nitems64 = (int64_t)F * ntiles;
+    if (nitems64 > (1LL << 30))
+        return hipErrorInvalidValue;
+    const int nitems = (int)nitems64;
+    const int bps = bits == 4 ? 1 : 2;
+    const int vec_ok = ((int64_t)N * bps % 16 == 0) && ((uintptr_t)volts % 16 == 0);
+    dim3 grid(xcd_grid(nitems)), block(kThreads);
+    auto kern = bits == 4 ? (vec_ok ? xc_plain_kernel<4, 1> : xc_plain_kernel<4, 0>)
+                          : (vec_ok ? xc_plain_kernel<8, 1> : xc_plain_kernel<8, 0>);
+    hipLaunchKernelGGL(kern, grid, block, 0, s, volts, T, F, N, ntiles, nitems, acc, accumulate);
+    return hipGetLastError();
+}
+
+template <int D, int KC>
+static hipError_t launch_mfma4_t(const Plan &pl, const uint8_t *volts, int64_t T, int F, int N,
+                                 int2 *acc, int accumulate, hipStream_t s)
+{
+    const int64_t nitems64 = (int64_t)F * pl.regions;
+    if (nitems64 > (1LL << 30))
+        return hipErrorInvalidValue;
+    const int nitems = (int)nitems64;
+    const int vec_ok = (N % 16 == 0) && ((uintptr_t)volts % 16 == 0);
+    dim3 grid(xcd_grid(nitems)), block(kThreads);
+    auto kern = vec_ok ? xc_mfma4_kernel<D, KC, 1> : xc_mfma4_kernel<D, KC, 0>;
+    hipLaunchKernelGGL(kern, grid, block, 0, s, volts, T, F, N, pl.nseg, pl.regions, nitems, acc,
+                       accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_mfma4(const Plan &pl, int kc, const uint8_t *volts, int64_t T, int F, int N,
+                        int2 *acc, int accumulate, hipStream_t s)
+{
+    if (kc != 64 || !plan_supported(N, pl.D))
+        return hipErrorInvalidValue;
+    switch (pl.D) {
+    case 1: return launch_mfma4_t<1, 64>(pl, volts, T, F, N, acc, accumulate, s);
+    case 2: return launch_mfma4_t<2, 64>(pl, volts, T, F, N, acc, accumulate, s);
+    case 3: return launch_mfma4_t<3, 64>(pl, volts, T, F, N, acc, accumulate, s);
+    case 4: return launch_mfma4_t<4, 64>(pl, volts, T, F, N, acc, accumulate, s);
+    case 5: return launch_mfma4_t<5, 64>(pl, volts, T, F, N, acc, accumulate, s);
+    case 6: return launch_mfma4_t<6, 64>(pl, volts, T, F, N, acc, accumulate, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_dump(const void *acc, void *out, int64_t bytes, int empty, hipStream_t s)
+{
+    if (bytes % 8 || (uintptr_t)acc % 16 || (uintptr_t)out % 16)
+        return hipErrorInvalidValue;
+    const int64_t n8 = bytes / 8;
+    const int64_t work = std::max<int64_t>(1, (n8 / 2 + kThreads - 1) / kThreads);
+    const int blocks = (int)std::min<int64_t>(work, 8192);
+    hipLaunchKernelGGL(xc_dump_kernel, dim3(blocks), dim3(kThreads), 0, s,
+                       reinterpret_cast<const int2 *>(acc), reinterpret_cast<int2 *>(out), n8, empty);
+    return hipGetLastError();
+}
+
+}  // namespace xc

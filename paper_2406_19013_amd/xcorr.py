@@ -1,0 +1,229 @@
+"""ctypes binding of libxcorr.so (argument marshalling only).
+
+The functions carry the C names of include/xcorr.h.  Device buffers are torch
+tensors (their data_ptr is passed), streams are torch streams (their raw
+hipStream_t is passed); every step of the computation runs in the library's
+HIP kernels.  A missing library is an error: there is no other code path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libxcorr.so")
+
+XCORR_OK = 0
+XCORR_E_INVAL = -1
+XCORR_E_NOMEM = -2
+XCORR_E_OVERFLOW = -3
+XCORR_E_HIP = -4
+XCORR_E_DEVICE = -5
+
+PATH_PLAIN = 0
+PATH_I8_MFMA = 1
+PATH_F16_MFMA = 2
+LAYOUT_TFN = 0
+
+TMAX_4BIT = 16_777_215
+TMAX_8BIT = 66_572
+
+
+class XcorrError(RuntimeError):
+    def __init__(self, code: int, where: str, detail: str = ""):
+        self.code = code
+        msg = f"{where} failed: {code} ({_strerror(code)})"
+        if detail:
+            msg += f": {detail}"
+        super().__init__(msg)
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("n_inputs", ctypes.c_int32),
+        ("n_chans", ctypes.c_int32),
+        ("sample_bits", ctypes.c_int32),
+        ("path", ctypes.c_int32),
+        ("layout", ctypes.c_int32),
+        ("tile", ctypes.c_int32),
+        ("max_samples_per_dump", ctypes.c_int64),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("samples_integrated", ctypes.c_int64),
+        ("samples_total", ctypes.c_int64),
+        ("ingests", ctypes.c_int64),
+        ("dumps", ctypes.c_int64),
+        ("kernel_launches", ctypes.c_int64),
+        ("seq_gaps", ctypes.c_uint64),
+        ("seq_gaps_total", ctypes.c_uint64),
+        ("tile", ctypes.c_int32),
+        ("regions_per_chan", ctypes.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lock = threading.Lock()
+_lib = None
+
+
+def load(path: str | None = None):
+    """Open libxcorr.so and declare its entry points (raises if it is missing)."""
+    global _lib
+    with _lock:
+        if _lib is not None and path is None:
+            return _lib
+        p = path or LIB_PATH
+        if not os.path.exists(p):
+            raise FileNotFoundError(
+                f"{p} is not built; run paper_2406_19013_amd.build.build() (hipcc, gfx950)")
+        lib = ctypes.CDLL(p)
+        vp, i64, u64, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t
+        cfgp = ctypes.POINTER(Config)
+        sig = {
+            "xcorr_query": [cfgp, ctypes.POINTER(sz), ctypes.POINTER(sz), ctypes.POINTER(i64)],
+            "xcorr_init": [cfgp, vp, sz, ctypes.POINTER(vp)],
+            "xcorr_ingest": [vp, vp, i64, u64, vp],
+            "xcorr_dump": [vp, vp, ctypes.POINTER(i64), ctypes.POINTER(u64), vp],
+            "xcorr_stats": [vp, ctypes.POINTER(Stats)],
+            "xcorr_destroy": [vp],
+        }
+        for name, args in sig.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        lib.xcorr_strerror.argtypes = [ctypes.c_int]
+        lib.xcorr_strerror.restype = ctypes.c_char_p
+        lib.xcorr_last_error.argtypes = []
+        lib.xcorr_last_error.restype = ctypes.c_char_p
+        if path is None:
+            _lib = lib
+        return lib
+
+
+def _strerror(code: int) -> str:
+    try:
+        return load().xcorr_strerror(code).decode()
+    except Exception:
+        return "?"
+
+
+def _check(rc: int, where: str):
+    if rc != XCORR_OK:
+        raise XcorrError(rc, where, load().xcorr_last_error().decode())
+
+
+def make_config(n_inputs: int, n_chans: int, sample_bits: int = 4, path: int = PATH_I8_MFMA,
+                tile: int = 0, max_samples_per_dump: int = 0, layout: int = LAYOUT_TFN) -> Config:
+    return Config(n_inputs, n_chans, sample_bits, path, layout, tile, max_samples_per_dump)
+
+
+def xcorr_query(cfg: Config):
+    """(workspace_bytes, out_bytes, t_max) for a config; raises XcorrError."""
+    ws, out, tmax = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_int64()
+    _check(load().xcorr_query(ctypes.byref(cfg), ctypes.byref(ws), ctypes.byref(out), ctypes.byref(tmax)),
+           "xcorr_query")
+    return ws.value, out.value, tmax.value
+
+
+def _stream_handle(stream) -> int | None:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream or None
+    if isinstance(stream, int):
+        return stream or None
+    return stream.cuda_stream or None
+
+
+def xcorr_init(cfg: Config, workspace, ws_bytes: int | None = None) -> ctypes.c_void_p:
+    """Create a context borrowing `workspace` (a device tensor)."""
+    ctx = ctypes.c_void_p()
+    nbytes = ws_bytes if ws_bytes is not None else workspace.numel() * workspace.element_size()
+    _check(load().xcorr_init(ctypes.byref(cfg), ctypes.c_void_p(workspace.data_ptr()), nbytes,
+                             ctypes.byref(ctx)), "xcorr_init")
+    return ctx
+
+
+def xcorr_ingest(ctx, volts, n_samples: int, seq: int = 0, stream=None):
+    _check(load().xcorr_ingest(ctx, ctypes.c_void_p(volts.data_ptr()), int(n_samples), int(seq),
+                               _stream_handle(stream)), "xcorr_ingest")
+
+
+def xcorr_dump(ctx, out, stream=None):
+    """Dump into the device tensor `out`; returns (n_integrated, n_gaps)."""
+    n, g = ctypes.c_int64(), ctypes.c_uint64()
+    _check(load().xcorr_dump(ctx, ctypes.c_void_p(out.data_ptr()), ctypes.byref(n), ctypes.byref(g),
+                             _stream_handle(stream)), "xcorr_dump")
+    return n.value, g.value
+
+
+def xcorr_stats(ctx) -> dict:
+    st = Stats()
+    _check(load().xcorr_stats(ctx, ctypes.byref(st)), "xcorr_stats")
+    return st.as_dict()
+
+
+def xcorr_destroy(ctx):
+    _check(load().xcorr_destroy(ctx), "xcorr_destroy")
+
+
+def xcorr_strerror(code: int) -> str:
+    return load().xcorr_strerror(code).decode()
+
+
+def xcorr_last_error() -> str:
+    return load().xcorr_last_error().decode()
+
+
+class Correlator:
+    """One context plus its device workspace (allocated with torch).
+
+    ``ingest(volts)`` takes a device tensor [T][F][N] (uint8, 4+4-bit) or
+    [T][F][N][2] (int8, 8+8-bit); ``dump()`` returns a new device tensor
+    [F][P][2] (int32, or float32 for the FP16 path).
+    """
+
+    def __init__(self, n_inputs: int, n_chans: int, sample_bits: int = 4, path: int = PATH_I8_MFMA,
+                 tile: int = 0, max_samples_per_dump: int = 0, device="cuda"):
+        import torch
+        self.cfg = make_config(n_inputs, n_chans, sample_bits, path, tile, max_samples_per_dump)
+        self.ws_bytes, self.out_bytes, self.t_max = xcorr_query(self.cfg)
+        self.device = torch.device(device)
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.ctx = xcorr_init(self.cfg, self.workspace, self.ws_bytes)
+        self.n_inputs, self.n_chans, self.sample_bits, self.path = n_inputs, n_chans, sample_bits, path
+        self.n_pairs = n_inputs * (n_inputs + 1) // 2
+        self._seq = 0
+
+    def ingest(self, volts, n_samples: int | None = None, seq: int | None = None, stream=None):
+        n = volts.shape[0] if n_samples is None else n_samples
+        s = self._seq if seq is None else seq
+        xcorr_ingest(self.ctx, volts, n, s, stream)
+        self._seq = s + 1
+
+    def dump(self, out=None, stream=None):
+        import torch
+        if out is None:
+            dt = torch.float32 if self.path == PATH_F16_MFMA else torch.int32
+            out = torch.empty((self.n_chans, self.n_pairs, 2), dtype=dt, device=self.device)
+        n, gaps = xcorr_dump(self.ctx, out, stream)
+        return out, n, gaps
+
+    def stats(self) -> dict:
+        return xcorr_stats(self.ctx)
+
+    def close(self):
+        if self.ctx:
+            xcorr_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

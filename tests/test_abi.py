@@ -1,0 +1,92 @@
+"""The C-ABI library on the CPU: it loads, exports what include/xcorr.h
+declares, and its pure-host calls validate and size correctly.  No device
+call is made here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2406_19013_amd import xcorr as X
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names += re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(xcorr_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return X.load()
+
+
+def test_library_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 8
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in include/ but not exported"
+
+
+def test_query_sizes_follow_eq1(lib):
+    # Eq. 1 of Section 2.2: N(N+1)/2 * f_ch * 2 * f_b bytes per integration
+    for N, F in ((192, 1024), (16, 8), (512, 128), (1, 1), (97, 3)):
+        ws, out, tmax = X.xcorr_query(X.make_config(N, F, 4, X.PATH_I8_MFMA))
+        assert out == N * (N + 1) // 2 * F * 2 * 4
+        assert ws >= out and ws % 256 == 0
+        assert tmax == X.TMAX_4BIT
+    assert X.xcorr_query(X.make_config(192, 1024))[1] == 151_781_376
+    _, _, t8 = X.xcorr_query(X.make_config(192, 512, 8, X.PATH_PLAIN))
+    assert t8 == X.TMAX_8BIT
+
+
+def test_tmax_constants_are_the_int32_bounds():
+    # 4-bit: worst sample contributes 2*8*8 = 128; 8-bit: 2*127^2 (-128 excluded)
+    assert X.TMAX_4BIT == (2 ** 31 - 1) // 128
+    assert X.TMAX_8BIT == (2 ** 31 - 1) // (2 * 127 * 127)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n_inputs=0, n_chans=4), X.XCORR_E_INVAL),
+    (dict(n_inputs=4, n_chans=0), X.XCORR_E_INVAL),
+    (dict(n_inputs=4, n_chans=4, sample_bits=5), X.XCORR_E_INVAL),
+    (dict(n_inputs=4, n_chans=4, path=7), X.XCORR_E_INVAL),
+    (dict(n_inputs=4, n_chans=4, layout=3), X.XCORR_E_INVAL),
+    (dict(n_inputs=4, n_chans=4, sample_bits=4, path=X.PATH_F16_MFMA), X.XCORR_E_INVAL),
+    (dict(n_inputs=192, n_chans=4, tile=5), X.XCORR_E_INVAL),
+    (dict(n_inputs=300, n_chans=4, tile=6), X.XCORR_E_INVAL),
+    (dict(n_inputs=4, n_chans=4, max_samples_per_dump=X.TMAX_4BIT + 1), X.XCORR_E_OVERFLOW),
+    (dict(n_inputs=4, n_chans=4, max_samples_per_dump=-1), X.XCORR_E_INVAL),
+])
+def test_query_rejects(kw, code):
+    with pytest.raises(X.XcorrError) as ei:
+        X.xcorr_query(X.make_config(**kw))
+    assert ei.value.code == code
+
+
+def test_init_rejects_small_or_missing_workspace_before_any_device_call(lib):
+    cfg = X.make_config(16, 8)
+    ctx = ctypes.c_void_p()
+    assert lib.xcorr_init(ctypes.byref(cfg), None, 1 << 20, ctypes.byref(ctx)) == X.XCORR_E_NOMEM
+    assert lib.xcorr_init(ctypes.byref(cfg), ctypes.c_void_p(256), 16, ctypes.byref(ctx)) == X.XCORR_E_NOMEM
+    assert lib.xcorr_init(ctypes.byref(cfg), ctypes.c_void_p(258), 1 << 20, ctypes.byref(ctx)) == X.XCORR_E_INVAL
+    assert not ctx.value
+
+
+def test_null_context_is_rejected(lib):
+    assert lib.xcorr_ingest(None, ctypes.c_void_p(256), 4, 0, None) == X.XCORR_E_INVAL
+    assert lib.xcorr_dump(None, ctypes.c_void_p(256), None, None, None) == X.XCORR_E_INVAL
+    assert lib.xcorr_destroy(None) == X.XCORR_E_INVAL
+    assert lib.xcorr_stats(None, None) == X.XCORR_E_INVAL
+
+
+def test_strerror_covers_codes():
+    for c in (0, -1, -2, -3, -4, -5):
+        assert X.xcorr_strerror(c) and X.xcorr_strerror(c) != "unknown error"
+    assert X.xcorr_strerror(-99) == "unknown error"
