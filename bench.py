@@ -1,0 +1,199 @@
+"""Benchmark of the X-engine hot path on one MI355X.
+
+A step is one integration of the benchmark workload through the whole hot
+path: ingest (HBM read of packed 4+4-bit voltages, unpack/corner turn in LDS,
+int8 MFMA contraction, int32 accumulation) followed by dump (accumulators to
+the caller's [F][P][2] buffer).
+
+Workload: 192 inputs (96 dual-polarisation feeds), 1024 channels, 4096
+samples per channel, 4+4-bit Gaussian noise (sigma 2.5) plus a common tone,
+generated on the device from a fixed seed.  The data span of one step is
+4096 / (125 MHz / 1024) = 33.55 ms of sky.
+
+Prints one JSON line: complex MAC/s of the int8-MFMA path, the real-time
+factor of the MFMA and plain paths, p50/p99 step latency, the roofline of the
+dominant kernel from HIP events on its launch stream, and the CPU oracle's
+rate on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N_INPUTS, N_CHANS, N_SAMPLES = 192, 1024, 4096
+BANDWIDTH_HZ = 125e6
+INT8_PEAK_TOPS = 5000.0       # MI355X dense int8 MFMA, 10^12 ops/s
+HBM_PEAK_GBS = 8000.0
+OPS_PER_CMAC = 8              # one complex multiply-accumulate = 4 real MACs
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def kernel_source_sha() -> str:
+    p = os.path.join(ROOT, "paper_2406_19013_amd", "csrc", "xcorr_kernels.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(per_launch_algo_bytes: float):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, if it was taken on the current
+    kernel source; else None."""
+    p = os.path.join(PROFILES, "xc_mfma4_tianlai_traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except ValueError:
+        return None
+    if d.get("kernel_src_sha") != kernel_source_sha():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(volts_dev, n_chan_sample: int):
+    """The oracle as it stands, on a channel subset, one thread per channel
+    slice on the host cores."""
+    import concurrent.futures as cf
+
+    import numpy as np
+
+    import oracle
+
+    cores = min(16, len(os.sched_getaffinity(0)))
+    sub = volts_dev[:, :n_chan_sample, :].contiguous().cpu().numpy()
+    T, F, N = sub.shape
+    lib = oracle.load_library()
+    chans = np.arange(F)
+    slices = [chans[k::cores] for k in range(cores)]
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(cores) as ex:
+        list(ex.map(lambda c: oracle.xcorr(sub, 4, T, F, N, chans=c, lib=lib), slices))
+    dt = time.perf_counter() - t0
+    cmacs = F * (N * (N + 1) // 2) * T
+    return {"value": cmacs / dt, "unit": "CMAC/s", "cores": cores, "kind": "oracle",
+            "sample": f"{N} inputs x {F} of {N_CHANS} channels x {T} samples "
+                      f"({cmacs:.3e} CMAC) in {dt:.2f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--plain-steps", type=int, default=3)
+    ap.add_argument("--cpu-channels", type=int, default=128)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tile", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the X-engine shards by channel with no cross-GPU "
+              "reduction, so --gpus above 1 is not run here", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2406_19013_amd import synth
+    from paper_2406_19013_amd import xcorr as X
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.Stream(device=dev)
+    N, F, T = N_INPUTS, N_CHANS, N_SAMPLES
+    P = N * (N + 1) // 2
+    cmac_per_step = P * F * T
+    span_s = T / (BANDWIDTH_HZ / F)
+
+    with torch.cuda.stream(stream):
+        volts = synth.tianlai(device=dev)
+    stream.synchronize()
+    mf = X.Correlator(N, F, 4, X.PATH_I8_MFMA, tile=args.tile, device=dev)
+    out = torch.empty((F, P, 2), dtype=torch.int32, device=dev)
+
+    def step(c, ev=None):
+        if ev:
+            ev[0].record(stream)
+        c.ingest(volts, T, stream=stream)
+        if ev:
+            ev[1].record(stream)
+        c.dump(out, stream=stream)
+        if ev:
+            ev[2].record(stream)
+
+    for _ in range(args.warmup):
+        step(mf)
+    stream.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(mf, evs[k])
+    stream.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ingest_ms = np.array([e[0].elapsed_time(e[1]) for e in evs])
+    dump_ms = np.array([e[1].elapsed_time(e[2]) for e in evs])
+    step_ms = ingest_ms + dump_ms
+    ms_per_step = wall * 1e3 / args.steps
+
+    # plain VALU path on the same data, same GPU
+    pl = X.Correlator(N, F, 4, X.PATH_PLAIN, device=dev)
+    step(pl)
+    stream.synchronize()
+    pev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.plain_steps)]
+    for k in range(args.plain_steps):
+        step(pl, pev[k])
+    stream.synchronize()
+    plain_ms = float(np.mean([e[0].elapsed_time(e[2]) for e in pev])) if pev else float("nan")
+    pl.close()
+
+    ingest_s = float(ingest_ms.mean()) / 1e3
+    algo_ops = OPS_PER_CMAC * cmac_per_step
+    achieved_tops = algo_ops / ingest_s / 1e12
+    in_bytes = T * F * N
+    acc_bytes = F * P * 8
+    traffic = measured_traffic(in_bytes + acc_bytes)
+    dump_gbs = 2 * acc_bytes / (float(dump_ms.mean()) / 1e3) / 1e9
+
+    result = {
+        "metric": "complex MAC/s (int8 MFMA path), real-time factor vs plain path, p99 step latency",
+        "value": cmac_per_step / (ms_per_step / 1e3),
+        "unit": "CMAC/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8",
+        "data": "synthetic",
+        "config": {"workload": "tianlai-192in-1024ch-4096t-4bit", "n_inputs": N, "n_chans": F,
+                   "n_samples": T, "sample_bits": 4, "tile": mf.stats()["tile"],
+                   "regions_per_chan": mf.stats()["regions_per_chan"]},
+        "rtf": {"int8_mfma": span_s / (ms_per_step / 1e3), "plain": span_s / (plain_ms / 1e3),
+                "data_span_ms": span_s * 1e3},
+        "plain_path": {"ms_per_step": plain_ms, "cmac_per_s": cmac_per_step / (plain_ms / 1e3)},
+        "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
+                       "ingest_mean": float(ingest_ms.mean()), "dump_mean": float(dump_ms.mean())},
+        "dump_hbm_gbs": dump_gbs,
+        "roofline": {"bound": "mfma", "achieved": achieved_tops, "peak": INT8_PEAK_TOPS,
+                     "unit": "TFLOP/s", "frac": achieved_tops / INT8_PEAK_TOPS, "traffic": traffic,
+                     "kernel": "xc_mfma4_kernel", "algorithmic_ops_per_launch": algo_ops,
+                     "hbm_algorithmic_bytes_per_launch": in_bytes + acc_bytes,
+                     "hbm_frac": (in_bytes + acc_bytes) / ingest_s / 1e9 / HBM_PEAK_GBS},
+    }
+    mf.close()
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(volts, args.cpu_channels)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -196,58 +196,38 @@ __device__ __forceinline__ v4i frag_tr8(const uint8_t *p, int eight_rows)
     return v4i{lo.x, lo.y, hi.x, hi.y};
 }
 
-// A nibble moved into the high half of a byte reads as 16x its value: the
-// real part is x & 0xF0 (shift 0), the imaginary part (x << 4) & 0xF0.
-__device__ __forceinline__ v4i nib16(v4i x, int shift) { return (x << shift) & (int)0xF0F0F0F0; }
-
 __device__ __forceinline__ v16i mfma_i8(v4i a, v4i b, v16i c)
 {
     return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
 }
 
-// Wave roles: which real product a wave accumulates, and the nibble shifts of
-// its A (row) and B (column) operands.
+// Wave roles: which real product a wave accumulates.  A role fixes the nibble
+// of its row (A) and column (B) operands: 0 = real part, 4 = imaginary part.
 enum Role { kRR = 0, kII = 1, kIR = 2, kRI = 3 };
-__device__ __forceinline__ int role_shift_a(int role) { return (role == kII || role == kIR) ? 4 : 0; }
-__device__ __forceinline__ int role_shift_b(int role) { return (role == kII || role == kRI) ? 4 : 0; }
+constexpr int role_shift_a(int role) { return (role == kII || role == kIR) ? 4 : 0; }
+constexpr int role_shift_b(int role) { return (role == kII || role == kRI) ? 4 : 0; }
 
-// One 32-sample K step over a region.  TRI: d x d blocks from LDS column 0,
-// tiles (I, J <= I).  RECT: D row blocks from LDS column 0 by D column blocks
-// from LDS column 32*D, all D*D tiles.  Tile t of the accumulator array is
-// (I, J) in row-major order of the region's active tiles.
-template <int D, bool TRI>
-__device__ __forceinline__ void k_step(const uint8_t *base, int S, int sa, int sb, v16i *acc)
+template <int SHIFT>
+__device__ __forceinline__ v4i nib16(v4i x)
 {
-    if constexpr (TRI) {
-        // row by row: only the column operands of rows <= I stay live
-        v4i B[D];
-        int t = 0;
-#pragma unroll
-        for (int I = 0; I < D; ++I) {
-            const v4i x = frag_tr8(base + 32 * I, 8 * S);
-            const v4i A = nib16(x, sa);
-            B[I] = nib16(x, sb);
-#pragma unroll
-            for (int J = 0; J <= I; ++J, ++t)
-                acc[t] = mfma_i8(A, B[J], acc[t]);
-        }
-    } else {
-        v4i A[D], B[D];
-#pragma unroll
-        for (int I = 0; I < D; ++I)
-            A[I] = nib16(frag_tr8(base + 32 * I, 8 * S), sa);
-#pragma unroll
-        for (int J = 0; J < D; ++J)
-            B[J] = nib16(frag_tr8(base + 32 * D + 32 * J, 8 * S), sb);
-        int t = 0;
-#pragma unroll
-        for (int I = 0; I < D; ++I)
-#pragma unroll
-            for (int J = 0; J < D; ++J, ++t)
-                acc[t] = mfma_i8(A[I], B[J], acc[t]);
-    }
+    if constexpr (SHIFT == 0)
+        return x & (int)0xF0F0F0F0;
+    else
+        return (x << 4) & (int)0xF0F0F0F0;
 }
 
+// LDS layout of one staged chunk: KC time rows of 256 bytes, i.e. 16 units of
+// 16 bytes.  Unit p of a row holds inputs 16p..16p+15 of the region (units
+// 0..2D-1: row blocks, 2D..4D-1: column blocks of a rectangle).  Unit p of row
+// r is stored at position p ^ ((r & 7) << 1), so that the 8 rows x 2 units a
+// transpose-read of two 16-lane groups touches fall on 16 distinct positions
+// (64 distinct banks).
+constexpr int kRowBytes = 256;
+
+// Tiles of a region: TRI = the D(D+1)/2 tiles (I, J <= I) of D x D blocks;
+// RECT = all D*D tiles of D row blocks by D column blocks.  Tile t is (I, J) in
+// row-major order.  The 8 waves of a work-group are (role, half): half 0 owns
+// tiles [0, NT/2), half 1 owns [NT/2, NT).
 constexpr int tri_I(int t)
 {
     int I = 0;
@@ -256,81 +236,182 @@ constexpr int tri_I(int t)
     return I;
 }
 constexpr int tri_J(int t) { return t - tri_I(t) * (tri_I(t) + 1) / 2; }
+constexpr int n_tiles(int D, bool tri) { return tri ? D * (D + 1) / 2 : D * D; }
+constexpr int tile_I(int D, bool tri, int t) { return tri ? tri_I(t) : t / D; }
+constexpr int tile_J(int D, bool tri, int t) { return tri ? tri_J(t) : t % D; }
+constexpr int half_begin(int D, bool tri, int h) { return h ? n_tiles(D, tri) / 2 : 0; }
+constexpr int half_end(int D, bool tri, int h) { return h ? n_tiles(D, tri) : n_tiles(D, tri) / 2; }
+// LDS block index of a tile's row / column operand
+constexpr int row_block(int D, bool tri, int t) { return tile_I(D, tri, t); }
+constexpr int col_block(int D, bool tri, int t) { return tri ? tile_J(D, tri, t) : D + tile_J(D, tri, t); }
+constexpr bool half_uses_row(int D, bool tri, int h, int b)
+{
+    for (int t = half_begin(D, tri, h); t < half_end(D, tri, h); ++t)
+        if (row_block(D, tri, t) == b)
+            return true;
+    return false;
+}
+constexpr bool half_uses_col(int D, bool tri, int h, int b)
+{
+    for (int t = half_begin(D, tri, h); t < half_end(D, tri, h); ++t)
+        if (col_block(D, tri, t) == b)
+            return true;
+    return false;
+}
 
-constexpr int mfma4_lds_row(int D) { return 32 * D * (D <= 4 ? 2 : 1) + 16; }
+// One 32-sample K step of one wave: read each LDS block the wave's tiles
+// touch once (two transpose reads), unpack the nibble(s) its role needs, and
+// issue its tiles' MFMAs.  `base` = chunk buffer + lane row offset; colo[b] =
+// the lane's swizzled byte offset of block b.
+template <int D, bool TRI, int ROLE, int HALF>
+__device__ __forceinline__ void k_step(const uint8_t *base, const int *colo, v16i *acc)
+{
+    constexpr int NB = TRI ? D : 2 * D;
+    constexpr int T0 = half_begin(D, TRI, HALF), T1 = half_end(D, TRI, HALF);
+    constexpr int SA = role_shift_a(ROLE), SB = role_shift_b(ROLE);
+    v4i A[NB], B[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const bool ua = half_uses_row(D, TRI, HALF, b), ub = half_uses_col(D, TRI, HALF, b);
+        if (ua || ub) {
+            const v4i x = frag_tr8(base + colo[b], 8 * kRowBytes);
+            if (ua)
+                A[b] = nib16<SA>(x);
+            if (ub)
+                B[b] = (ua && SA == SB) ? A[b] : nib16<SB>(x);
+        }
+    }
+#pragma unroll
+    for (int t = T0; t < T1; ++t)
+        acc[t - T0] = mfma_i8(A[row_block(D, TRI, t)], B[col_block(D, TRI, t)], acc[t - T0]);
+}
 
-// Whole work-group body for one region shape.  row_blk / col_blk: first
-// 32-input block of the region's rows / columns.
-template <int D, bool TRI, int KC, int VEC>
+// s_waitcnt with only the vector-memory counter constrained (gfx9 encoding:
+// vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt out of range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+constexpr int kBufferOutOfRange = (int)0xFFFFFFF0;  // any offset >= num_records reads 0
+
+// Work-group barrier without the release/acquire fence of __syncthreads (the
+// fence would wait for every LDS-DMA load in flight, i.e. drain the ring).
+// The "memory" clobber keeps the compiler from moving LDS accesses across it;
+// loads whose data must be visible are waited for explicitly before it.
+__device__ __forceinline__ void barrier_no_fence() { asm volatile("s_barrier" ::: "memory"); }
+
+constexpr int kMfmaThreads = 512;   // 8 waves: (role, half)
+
+// Whole work-group body for one region shape and one wave (role, half).
+// row_blk / col_blk: first 32-input block of the region's rows / columns.
+//
+// VEC = 1 (N a multiple of 16, 16-byte aligned input): chunks of KC time rows
+// go HBM -> LDS by buffer_load_dwordx4 ... lds into a ring of NBUF buffers,
+// NBUF-1 chunks ahead of the MFMAs; the buffer descriptor of each chunk ends at
+// the last valid time row, and inputs >= N use an out-of-range offset, so the
+// hardware supplies the zero padding.  VEC = 0: each chunk is staged through
+// registers, with byte loads for the ragged row end.
+template <int D, bool TRI, int KC, int NBUF, int VEC, int ROLE, int HALF>
 __device__ __forceinline__ void mfma4_region(uint8_t *smem, const uint8_t *__restrict__ volts,
                                              int64_t T, int F, int N, int f, int row_blk, int col_blk,
                                              int2 *__restrict__ acc_out, int accumulate)
 {
-    constexpr int S = mfma4_lds_row(D);                 // LDS bytes per time row (+16 pad)
-    constexpr int NT = TRI ? D * (D + 1) / 2 : D * D;   // accumulator tiles per wave
-    constexpr int BUF = KC * S;
+    constexpr int NT = n_tiles(D, TRI);
+    constexpr int T0 = half_begin(D, TRI, HALF), T1 = half_end(D, TRI, HALF);
+    constexpr int NB = TRI ? D : 2 * D;                 // 32-input blocks staged per row
+    constexpr int BUF = KC * kRowBytes;
+    constexpr int LOADS = KC * 16 / kMfmaThreads;       // 16-byte units per thread per chunk
     constexpr int G = 4;                                // tiles per epilogue round
-    constexpr int NP = (TRI ? 2 : 4) * D;               // 16-byte fill pieces per time row
-    constexpr int PMAX = (KC * NP + kThreads - 1) / kThreads;
+    static_assert(LOADS * kMfmaThreads == KC * 16, "chunk must be a whole number of wave loads");
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wave = tid >> 6;
     const int g = lane >> 4, q = lane & 15;
-    const int frag_off = ((g >> 1) * 16 + (q >> 1)) * S + (g & 1) * 16 + (q & 1) * 8;
-    const int sa = role_shift_a(wave), sb = role_shift_b(wave);
 
-    // fixed assignment of 16-byte fill pieces to threads
-    int p_t[PMAX], p_i0[PMAX], p_lds[PMAX];
+    // operand read offsets: row (g>>1)*16 + q>>1 of the K step, unit 2b + (g&1)
+    const int row_off = ((g >> 1) * 16 + (q >> 1)) * kRowBytes + (q & 1) * 8;
+    int colo[NB];
 #pragma unroll
-    for (int k = 0; k < PMAX; ++k) {
-        const int pc = tid + kThreads * k;
-        const int t = pc / NP, p = pc - t * NP;
-        p_t[k] = pc < KC * NP ? t : -1;
-        p_i0[k] = p < 2 * D ? row_blk * 32 + p * 16 : col_blk * 32 + (p - 2 * D) * 16;
-        p_lds[k] = t * S + p * 16;
+    for (int b = 0; b < NB; ++b)
+        colo[b] = ((2 * b + (g & 1)) ^ (q & 14)) << 4;
+
+    // fill slots: unit U = (wave*LOADS + k)*64 + lane -> row U/16, position U%16
+    const int64_t row_bytes = (int64_t)F * N;
+    int voff[LOADS];
+#pragma unroll
+    for (int k = 0; k < LOADS; ++k) {
+        const int U = (wave * LOADS + k) * 64 + lane;
+        const int r = U >> 4;
+        const int p = (U & 15) ^ ((r & 7) << 1);
+        const int i0 = p < 2 * D ? row_blk * 32 + 16 * p : col_blk * 32 + 16 * (p - 2 * D);
+        const bool valid = p < 2 * NB && i0 < N;
+        voff[k] = valid ? (int)(r * row_bytes + (int64_t)f * N + i0) : kBufferOutOfRange;
     }
 
-    v16i acc[NT];
+    v16i acc[T1 > T0 ? T1 - T0 : 1];   // a half may own no tile (D = 1)
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+    for (int t = 0; t < (T1 > T0 ? T1 - T0 : 1); ++t)
         acc[t] = v16i{};
 
     const int64_t nchunks = (T + KC - 1) / KC;
-    v4i pre[PMAX];
-    auto load_chunk = [&](int64_t c) {
+
+    auto issue = [&](int64_t c) {
+        const int64_t rows = min((int64_t)KC, T - c * KC);
+        __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(volts + c * KC * row_bytes), (short)0, (int)(rows * row_bytes), 0x00020000);
+        uint8_t *dst = smem + (int)(c % NBUF) * BUF + wave * LOADS * 1024;
 #pragma unroll
-        for (int k = 0; k < PMAX; ++k)
-            pre[k] = p_t[k] >= 0 ? load_piece(volts, c * KC + p_t[k], T, f, F, N, p_i0[k], 1, VEC)
-                                 : v4i{0, 0, 0, 0};
+        for (int k = 0; k < LOADS; ++k)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                rsrc, (__attribute__((address_space(3))) void *)(dst + k * 1024), 16, voff[k], 0, 0, 0);
     };
-    auto store_chunk = [&](int64_t c) {
-        uint8_t *buf = smem + (c & 1) * BUF;
+    auto fill_sync = [&](int64_t c) {
+        uint8_t *dst = smem + (int)(c % NBUF) * BUF;
 #pragma unroll
-        for (int k = 0; k < PMAX; ++k)
-            if (p_t[k] >= 0)
-                *reinterpret_cast<v4i *>(buf + p_lds[k]) = pre[k];
+        for (int k = 0; k < LOADS; ++k) {
+            const int U = (wave * LOADS + k) * 64 + lane;
+            const int r = U >> 4;
+            const int p = (U & 15) ^ ((r & 7) << 1);
+            const int i0 = p < 2 * D ? row_blk * 32 + 16 * p : col_blk * 32 + 16 * (p - 2 * D);
+            const v4i val = p < 2 * NB ? load_piece(volts, c * KC + r, T, f, F, N, i0, 1, 0)
+                                       : v4i{0, 0, 0, 0};
+            *reinterpret_cast<v4i *>(dst + U * 16) = val;
+        }
     };
 
-    if (nchunks > 0) {
-        load_chunk(0);
-        store_chunk(0);
+    if constexpr (VEC) {
+#pragma unroll
+        for (int c = 0; c < NBUF - 1; ++c)
+            if (c < nchunks)
+                issue(c);
     }
-    __syncthreads();
     for (int64_t c = 0; c < nchunks; ++c) {
-        if (c + 1 < nchunks)
-            load_chunk(c + 1);
-        const uint8_t *buf = smem + (c & 1) * BUF + frag_off;
+        if constexpr (VEC) {
+            if (c + NBUF - 2 < nchunks)
+                wait_vmcnt<LOADS * (NBUF - 2)>();
+            else
+                wait_vmcnt<0>();
+            barrier_no_fence();   // chunk c is in LDS; every wave is done with chunk c-1
+            if (c + NBUF - 1 < nchunks)
+                issue(c + NBUF - 1);   // into the buffer chunk c-1 used
+        } else {
+            __syncthreads();      // every wave is done with the buffer being refilled
+            fill_sync(c);
+            __syncthreads();
+        }
+        const uint8_t *buf = smem + (int)(c % NBUF) * BUF + row_off;
 #pragma unroll
         for (int ks = 0; ks < KC / 32; ++ks)
-            k_step<D, TRI>(buf + ks * 32 * S, S, sa, sb, acc);
-        if (c + 1 < nchunks)
-            store_chunk(c + 1);
-        __syncthreads();
+            k_step<D, TRI, ROLE, HALF>(buf + ks * 32 * kRowBytes, colo, acc);
     }
+    __syncthreads();
 
-    // Epilogue: the four waves' products meet in LDS, G tiles per round.
-    // 256*Re = RR + II and 256*Im = IR - RI; each product is a multiple of 256.
+    // Epilogue: the four roles' products of each tile meet in LDS, G tiles per
+    // round; 256*Re = RR + II and 256*Im = IR - RI (each a multiple of 256).
     int *stage = reinterpret_cast<int *>(smem);
     const int64_t P = (int64_t)N * (N + 1) / 2;
     int2 *out_f = acc_out + (int64_t)f * P;
@@ -338,11 +419,12 @@ __device__ __forceinline__ void mfma4_region(uint8_t *smem, const uint8_t *__res
     for (int t0 = 0; t0 < NT; t0 += G) {
 #pragma unroll
         for (int u = 0; u < G; ++u) {
-            if (t0 + u < NT) {
+            const int t = t0 + u;
+            if (t >= T0 && t < T1) {
 #pragma unroll
                 for (int rg = 0; rg < 16; ++rg) {
                     const int row = 8 * (rg >> 2) + 4 * (lane >> 5) + (rg & 3);
-                    stage[((wave * G + u) << 10) + row * 32 + (lane & 31)] = acc[t0 + u][rg];
+                    stage[((ROLE * G + u) << 10) + row * 32 + (lane & 31)] = acc[t - T0][rg];
                 }
             }
         }
@@ -351,18 +433,18 @@ __device__ __forceinline__ void mfma4_region(uint8_t *smem, const uint8_t *__res
         for (int u = 0; u < G; ++u) {
             const int t = t0 + u;
             if (t < NT) {
-                const int I = TRI ? tri_I(t) : t / D;
-                const int J = TRI ? tri_J(t) : t % D;
+                const int I = tile_I(D, TRI, t);
+                const int J = tile_J(D, TRI, t);
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int e = tid + kThreads * k;
+                for (int k = 0; k < 1024 / kMfmaThreads; ++k) {
+                    const int e = tid + kMfmaThreads * k;
                     const int i = (row_blk + I) * 32 + (e >> 5);
                     const int j = (col_blk + J) * 32 + (e & 31);
                     if (i < N && j <= i) {
-                        const int rr = stage[((0 * G + u) << 10) + e];
-                        const int ii = stage[((1 * G + u) << 10) + e];
-                        const int ir = stage[((2 * G + u) << 10) + e];
-                        const int ri = stage[((3 * G + u) << 10) + e];
+                        const int rr = stage[((kRR * G + u) << 10) + e];
+                        const int ii = stage[((kII * G + u) << 10) + e];
+                        const int ir = stage[((kIR * G + u) << 10) + e];
+                        const int ri = stage[((kRI * G + u) << 10) + e];
                         int re = (rr >> 8) + (ii >> 8);
                         int im = (ir >> 8) - (ri >> 8);
                         int2 *dst = out_f + (int64_t)i * (i + 1) / 2 + j;
@@ -380,19 +462,40 @@ __device__ __forceinline__ void mfma4_region(uint8_t *smem, const uint8_t *__res
     }
 }
 
+template <int D, bool TRI, int KC, int NBUF, int VEC>
+__device__ __forceinline__ void mfma4_dispatch(uint8_t *smem, const uint8_t *__restrict__ volts,
+                                               int64_t T, int F, int N, int f, int row_blk, int col_blk,
+                                               int2 *__restrict__ acc_out, int accumulate)
+{
+    // each wave runs one complete specialised body; all bodies execute the
+    // same sequence of work-group barriers
+    switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {
+#define XC_CASE(W)                                                                                  \
+    case W:                                                                                         \
+        mfma4_region<D, TRI, KC, NBUF, VEC, ((W) & 3), ((W) >> 2)>(smem, volts, T, F, N, f, row_blk,   \
+                                                             col_blk, acc_out, accumulate);        \
+        break;
+        XC_CASE(0) XC_CASE(1) XC_CASE(2) XC_CASE(3) XC_CASE(4) XC_CASE(5) XC_CASE(6) XC_CASE(7)
+#undef XC_CASE
+    default: break;
+    }
+}
+
+constexpr int kNBuf = 6;
+
 // One work-group per (channel, region).  Regions of one channel: nseg
 // triangles on the diagonal segments, then the nseg(nseg-1)/2 rectangles
 // (a, b), a > b, in row-major order.  Segments are D blocks each (the input
 // count is zero-padded up to 32*D*nseg).
 template <int D, int KC, int VEC>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
+__global__ __launch_bounds__(kMfmaThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void xc_mfma4_kernel(const uint8_t *__restrict__ volts, int64_t T, int F, int N, int nseg, int R,
                      int nitems, int2 *__restrict__ acc_out, int accumulate)
 {
-    constexpr int S = mfma4_lds_row(D);
+    constexpr int RING = kNBuf * KC * kRowBytes;
     constexpr int STAGE = 4 * 4 * 1024 * 4;
-    constexpr int SMEM = 2 * KC * S > STAGE ? 2 * KC * S : STAGE;
-    __shared__ __attribute__((aligned(16))) uint8_t smem[SMEM];
+    constexpr int SMEM = RING > STAGE ? RING : STAGE;
+    __shared__ __attribute__((aligned(1024))) uint8_t smem[SMEM];
 
     const int item = xcd_item();
     if (item >= nitems)
@@ -400,7 +503,7 @@ void xc_mfma4_kernel(const uint8_t *__restrict__ volts, int64_t T, int F, int N,
     const int f = item / R;
     const int r = item - f * R;
     if (r < nseg) {
-        mfma4_region<D, true, KC, VEC>(smem, volts, T, F, N, f, r * D, r * D, acc_out, accumulate);
+        mfma4_dispatch<D, true, KC, kNBuf, VEC>(smem, volts, T, F, N, f, r * D, r * D, acc_out, accumulate);
     } else if constexpr (D <= 4) {
         const int k = r - nseg;
         int a = (int)((1.f + sqrtf(1.f + 8.f * k)) * 0.5f);
@@ -409,7 +512,8 @@ void xc_mfma4_kernel(const uint8_t *__restrict__ volts, int64_t T, int F, int N,
         while ((a + 1) * a / 2 <= k)
             ++a;
         const int b = k - a * (a - 1) / 2;
-        mfma4_region<D, false, KC, VEC>(smem, volts, T, F, N, f, a * D, b * D, acc_out, accumulate);
+        mfma4_dispatch<D, false, KC, kNBuf, VEC>(smem, volts, T, F, N, f, a * D, b * D, acc_out,
+                                                 accumulate);
     }
 }
 
@@ -477,8 +581,10 @@ static hipError_t launch_mfma4_t(const Plan &pl, const uint8_t *volts, int64_t T
     if (nitems64 > (1LL << 30))
         return hipErrorInvalidValue;
     const int nitems = (int)nitems64;
-    const int vec_ok = (N % 16 == 0) && ((uintptr_t)volts % 16 == 0);
-    dim3 grid(xcd_grid(nitems)), block(kThreads);
+    // the LDS-DMA path addresses one chunk of KC time rows with 32-bit offsets
+    const int vec_ok = (N % 16 == 0) && ((uintptr_t)volts % 16 == 0) &&
+                       (int64_t)KC * F * N < (1LL << 31) - 16;
+    dim3 grid(xcd_grid(nitems)), block(kMfmaThreads);
     auto kern = vec_ok ? xc_mfma4_kernel<D, KC, 1> : xc_mfma4_kernel<D, KC, 0>;
     hipLaunchKernelGGL(kern, grid, block, 0, s, volts, T, F, N, pl.nseg, pl.regions, nitems, acc,
                        accumulate);
