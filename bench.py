@@ -89,6 +89,7 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--cpu-channels", type=int, default=128)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain-path comparison")
     ap.add_argument("--tile", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -143,15 +144,17 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
 
     # plain VALU path on the same data, same GPU
-    pl = X.Correlator(N, F, 4, X.PATH_PLAIN, device=dev)
-    step(pl)
-    stream.synchronize()
-    pev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.plain_steps)]
-    for k in range(args.plain_steps):
-        step(pl, pev[k])
-    stream.synchronize()
-    plain_ms = float(np.mean([e[0].elapsed_time(e[2]) for e in pev])) if pev else float("nan")
-    pl.close()
+    plain_ms = float("nan")
+    if not args.no_plain and args.plain_steps > 0:
+        pl = X.Correlator(N, F, 4, X.PATH_PLAIN, device=dev)
+        step(pl)
+        stream.synchronize()
+        pev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.plain_steps)]
+        for k in range(args.plain_steps):
+            step(pl, pev[k])
+        stream.synchronize()
+        plain_ms = float(np.mean([e[0].elapsed_time(e[2]) for e in pev]))
+        pl.close()
 
     ingest_s = float(ingest_ms.mean()) / 1e3
     algo_ops = OPS_PER_CMAC * cmac_per_step

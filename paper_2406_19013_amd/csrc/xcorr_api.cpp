@@ -170,6 +170,10 @@ int xcorr_init(const xcorr_config *cfg, void *d_workspace, size_t ws_bytes, xcor
         if (!tile)
             tile = default_tile(cfg->n_inputs);
         c->plan = xc::make_plan(cfg->n_inputs, tile);
+        // time rows staged per LDS chunk (64 or 128; 128 for D >= 4 only)
+        const char *v = std::getenv("XCORR_CHUNK");
+        if (v && std::strcmp(v, "128") == 0 && c->plan.D >= 4)
+            c->kc = 128;
     }
     c->ws = d_workspace;
     c->ws_bytes = ws_bytes;

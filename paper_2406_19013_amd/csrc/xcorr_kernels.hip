@@ -189,10 +189,16 @@ __global__ __launch_bounds__(kThreads) void xc_plain_kernel(
 // k-half l/32, 16 int8; result register r of lane l is row 8(r/4) + 4(l/32) +
 // r%4, column l%32.
 
-__device__ __forceinline__ v4i frag_tr8(const uint8_t *p, int eight_rows)
+typedef __attribute__((address_space(3))) uint8_t lds_u8;
+
+// Two transposing 8-byte reads, 8 time rows apart: the lane's 16 samples of
+// one input.  `p` is an LDS address; the row offsets fold into the
+// instructions' immediate offsets.
+template <int EIGHT_ROWS>
+__device__ __forceinline__ v4i frag_tr8(lds_u8 *p)
 {
     const v2i lo = __builtin_amdgcn_ds_read_tr8_b64_v2i32((lds_v2i *)p);
-    const v2i hi = __builtin_amdgcn_ds_read_tr8_b64_v2i32((lds_v2i *)(p + eight_rows));
+    const v2i hi = __builtin_amdgcn_ds_read_tr8_b64_v2i32((lds_v2i *)(p + EIGHT_ROWS));
     return v4i{lo.x, lo.y, hi.x, hi.y};
 }
 
@@ -207,14 +213,10 @@ enum Role { kRR = 0, kII = 1, kIR = 2, kRI = 3 };
 constexpr int role_shift_a(int role) { return (role == kII || role == kIR) ? 4 : 0; }
 constexpr int role_shift_b(int role) { return (role == kII || role == kRI) ? 4 : 0; }
 
-template <int SHIFT>
-__device__ __forceinline__ v4i nib16(v4i x)
-{
-    if constexpr (SHIFT == 0)
-        return x & (int)0xF0F0F0F0;
-    else
-        return (x << 4) & (int)0xF0F0F0F0;
-}
+// A nibble moved into the high half of a byte reads as 16x its value: the
+// real part is x & 0xF0, the imaginary part (x << 4) & 0xF0, both exact int8.
+__device__ __forceinline__ v4i re16(v4i x) { return x & (int)0xF0F0F0F0; }
+__device__ __forceinline__ v4i im16(v4i x) { return (x << 4) & (int)0xF0F0F0F0; }
 
 // LDS layout of one staged chunk: KC time rows of 256 bytes, i.e. 16 units of
 // 16 bytes.  Unit p of a row holds inputs 16p..16p+15 of the region (units
@@ -236,6 +238,15 @@ constexpr int tri_I(int t)
     return I;
 }
 constexpr int tri_J(int t) { return t - tri_I(t) * (tri_I(t) + 1) / 2; }
+// run-time versions (tile index not a compile-time constant)
+__device__ __forceinline__ int tri_I_rt(int t)
+{
+    int I = (int)((sqrtf(8.f * t + 1.f) - 1.f) * 0.5f);
+    I += (I + 1) * (I + 2) / 2 <= t;
+    I -= I * (I + 1) / 2 > t;
+    return I;
+}
+__device__ __forceinline__ int tri_J_rt(int t) { const int I = tri_I_rt(t); return t - I * (I + 1) / 2; }
 constexpr int n_tiles(int D, bool tri) { return tri ? D * (D + 1) / 2 : D * D; }
 constexpr int tile_I(int D, bool tri, int t) { return tri ? tri_I(t) : t / D; }
 constexpr int tile_J(int D, bool tri, int t) { return tri ? tri_J(t) : t % D; }
@@ -261,10 +272,10 @@ constexpr bool half_uses_col(int D, bool tri, int h, int b)
 
 // One 32-sample K step of one wave: read each LDS block the wave's tiles
 // touch once (two transpose reads), unpack the nibble(s) its role needs, and
-// issue its tiles' MFMAs.  `base` = chunk buffer + lane row offset; colo[b] =
-// the lane's swizzled byte offset of block b.
-template <int D, bool TRI, int ROLE, int HALF>
-__device__ __forceinline__ void k_step(const uint8_t *base, const int *colo, v16i *acc)
+// issue its tiles' MFMAs.  addr[b] = this lane's LDS address of block b in the
+// current chunk; KOFF = the K step's row offset.
+template <int D, bool TRI, int ROLE, int HALF, int KOFF>
+__device__ __forceinline__ void k_step(lds_u8 *const *addr, v16i *acc)
 {
     constexpr int NB = TRI ? D : 2 * D;
     constexpr int T0 = half_begin(D, TRI, HALF), T1 = half_end(D, TRI, HALF);
@@ -274,11 +285,11 @@ __device__ __forceinline__ void k_step(const uint8_t *base, const int *colo, v16
     for (int b = 0; b < NB; ++b) {
         const bool ua = half_uses_row(D, TRI, HALF, b), ub = half_uses_col(D, TRI, HALF, b);
         if (ua || ub) {
-            const v4i x = frag_tr8(base + colo[b], 8 * kRowBytes);
+            const v4i x = frag_tr8<8 * kRowBytes>(addr[b] + KOFF);
             if (ua)
-                A[b] = nib16<SA>(x);
+                A[b] = SA ? im16(x) : re16(x);
             if (ub)
-                B[b] = (ua && SA == SB) ? A[b] : nib16<SB>(x);
+                B[b] = (ua && SA == SB) ? A[b] : (SB ? im16(x) : re16(x));
         }
     }
 #pragma unroll
@@ -305,6 +316,21 @@ __device__ __forceinline__ void barrier_no_fence() { asm volatile("s_barrier" ::
 
 constexpr int kMfmaThreads = 512;   // 8 waves: (role, half)
 
+// Occupancy plan: regions of D <= 3 blocks fit 128 registers per wave, so two
+// work-groups share a CU (their barriers are independent, which hides LDS
+// latency); larger regions take the CU alone.  LDS per work-group holds the
+// ring of NBUF packed chunks; after the main loop it is reused as the
+// epilogue stage of G tiles x 4 products x 4 KB.
+constexpr int mfma4_wgs_per_cu(int D) { return D <= 3 ? 2 : 1; }
+constexpr int mfma4_nbuf(int D, int KC) { return D <= 3 ? 4 : (KC == 64 ? 6 : 3); }
+constexpr int mfma4_epilogue_tiles(int D) { return D <= 3 ? 4 : 7; }
+constexpr int mfma4_smem_bytes(int D, int KC)
+{
+    return mfma4_nbuf(D, KC) * KC * kRowBytes > mfma4_epilogue_tiles(D) * 16384
+               ? mfma4_nbuf(D, KC) * KC * kRowBytes
+               : mfma4_epilogue_tiles(D) * 16384;
+}
+
 // Whole work-group body for one region shape and one wave (role, half).
 // row_blk / col_blk: first 32-input block of the region's rows / columns.
 //
@@ -324,13 +350,14 @@ __device__ __forceinline__ void mfma4_region(uint8_t *smem, const uint8_t *__res
     constexpr int NB = TRI ? D : 2 * D;                 // 32-input blocks staged per row
     constexpr int BUF = KC * kRowBytes;
     constexpr int LOADS = KC * 16 / kMfmaThreads;       // 16-byte units per thread per chunk
-    constexpr int G = 4;                                // tiles per epilogue round
+    constexpr int G = mfma4_epilogue_tiles(D);          // tiles per epilogue round
     static_assert(LOADS * kMfmaThreads == KC * 16, "chunk must be a whole number of wave loads");
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int g = lane >> 4, q = lane & 15;
+    lds_u8 *const ring = (lds_u8 *)smem;
 
     // operand read offsets: row (g>>1)*16 + q>>1 of the K step, unit 2b + (g&1)
     const int row_off = ((g >> 1) * 16 + (q >> 1)) * kRowBytes + (q & 1) * 8;
@@ -357,29 +384,28 @@ __device__ __forceinline__ void mfma4_region(uint8_t *smem, const uint8_t *__res
     for (int t = 0; t < (T1 > T0 ? T1 - T0 : 1); ++t)
         acc[t] = v16i{};
 
-    const int64_t nchunks = (T + KC - 1) / KC;
-
-    auto issue = [&](int64_t c) {
-        const int64_t rows = min((int64_t)KC, T - c * KC);
+    const int nchunks = (int)((T + KC - 1) / KC);
+    auto issue = [&](int c, int bufi) {
+        const int64_t rows = min((int64_t)KC, T - (int64_t)c * KC);
         __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
-            (void *)(volts + c * KC * row_bytes), (short)0, (int)(rows * row_bytes), 0x00020000);
-        uint8_t *dst = smem + (int)(c % NBUF) * BUF + wave * LOADS * 1024;
+            (void *)(volts + (int64_t)c * KC * row_bytes), (short)0, (int)(rows * row_bytes), 0x00020000);
+        lds_u8 *dst = ring + bufi * BUF + wave * LOADS * 1024;
 #pragma unroll
         for (int k = 0; k < LOADS; ++k)
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                rsrc, (__attribute__((address_space(3))) void *)(dst + k * 1024), 16, voff[k], 0, 0, 0);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (__attribute__((address_space(3))) void *)(dst + k * 1024),
+                                                     16, voff[k], 0, 0, 0);
     };
-    auto fill_sync = [&](int64_t c) {
-        uint8_t *dst = smem + (int)(c % NBUF) * BUF;
+    auto fill_sync = [&](int c, int bufi) {
+        lds_u8 *dst = ring + bufi * BUF;
 #pragma unroll
         for (int k = 0; k < LOADS; ++k) {
             const int U = (wave * LOADS + k) * 64 + lane;
             const int r = U >> 4;
             const int p = (U & 15) ^ ((r & 7) << 1);
             const int i0 = p < 2 * D ? row_blk * 32 + 16 * p : col_blk * 32 + 16 * (p - 2 * D);
-            const v4i val = p < 2 * NB ? load_piece(volts, c * KC + r, T, f, F, N, i0, 1, 0)
+            const v4i val = p < 2 * NB ? load_piece(volts, (int64_t)c * KC + r, T, f, F, N, i0, 1, 0)
                                        : v4i{0, 0, 0, 0};
-            *reinterpret_cast<v4i *>(dst + U * 16) = val;
+            *(__attribute__((address_space(3))) v4i *)(dst + U * 16) = val;
         }
     };
 
@@ -387,9 +413,10 @@ __device__ __forceinline__ void mfma4_region(uint8_t *smem, const uint8_t *__res
 #pragma unroll
         for (int c = 0; c < NBUF - 1; ++c)
             if (c < nchunks)
-                issue(c);
+                issue(c, c);
     }
-    for (int64_t c = 0; c < nchunks; ++c) {
+    int bufc = 0;                 // ring slot of chunk c
+    for (int c = 0; c < nchunks; ++c) {
         if constexpr (VEC) {
             if (c + NBUF - 2 < nchunks)
                 wait_vmcnt<LOADS * (NBUF - 2)>();
@@ -397,24 +424,41 @@ __device__ __forceinline__ void mfma4_region(uint8_t *smem, const uint8_t *__res
                 wait_vmcnt<0>();
             barrier_no_fence();   // chunk c is in LDS; every wave is done with chunk c-1
             if (c + NBUF - 1 < nchunks)
-                issue(c + NBUF - 1);   // into the buffer chunk c-1 used
+                issue(c + NBUF - 1, bufc == 0 ? NBUF - 1 : bufc - 1);   // the slot chunk c-1 used
         } else {
-            __syncthreads();      // every wave is done with the buffer being refilled
-            fill_sync(c);
+            __syncthreads();      // every wave is done with the slot being refilled
+            fill_sync(c, bufc);
             __syncthreads();
         }
-        const uint8_t *buf = smem + (int)(c % NBUF) * BUF + row_off;
+        lds_u8 *addr[NB];
+        lds_u8 *const cb = ring + bufc * BUF + row_off;
 #pragma unroll
-        for (int ks = 0; ks < KC / 32; ++ks)
-            k_step<D, TRI, ROLE, HALF>(buf + ks * 32 * kRowBytes, colo, acc);
+        for (int b = 0; b < NB; ++b)
+            addr[b] = cb + colo[b];
+#pragma unroll
+        for (int ks = 0; ks < KC / 32; ++ks) {
+            if (ks == 0)
+                k_step<D, TRI, ROLE, HALF, 0>(addr, acc);
+            else if (ks == 1)
+                k_step<D, TRI, ROLE, HALF, 32 * kRowBytes>(addr, acc);
+            else if (ks == 2)
+                k_step<D, TRI, ROLE, HALF, 64 * kRowBytes>(addr, acc);
+            else
+                k_step<D, TRI, ROLE, HALF, 96 * kRowBytes>(addr, acc);
+        }
+        bufc = bufc + 1 == NBUF ? 0 : bufc + 1;
     }
-    __syncthreads();
+    __syncthreads();              // every wave is done with the ring
 
     // Epilogue: the four roles' products of each tile meet in LDS, G tiles per
     // round; 256*Re = RR + II and 256*Im = IR - RI (each a multiple of 256).
-    int *stage = reinterpret_cast<int *>(smem);
+    // Stage layout per (role, tile): [quad rq][lane][4] int32, so that a lane
+    // writes its registers 4..4rq+3 as one 16-byte store; result register r of
+    // lane l is row 8(r/4) + 4(l/32) + r%4, column l%32 of the tile.
+    typedef __attribute__((address_space(3))) v4i lds_v4i;
+    lds_v4i *const stage = (lds_v4i *)smem;
     const int64_t P = (int64_t)N * (N + 1) / 2;
-    int2 *out_f = acc_out + (int64_t)f * P;
+    int2 *const out_f = acc_out + (int64_t)f * P;
 #pragma unroll
     for (int t0 = 0; t0 < NT; t0 += G) {
 #pragma unroll
@@ -422,40 +466,42 @@ __device__ __forceinline__ void mfma4_region(uint8_t *smem, const uint8_t *__res
             const int t = t0 + u;
             if (t >= T0 && t < T1) {
 #pragma unroll
-                for (int rg = 0; rg < 16; ++rg) {
-                    const int row = 8 * (rg >> 2) + 4 * (lane >> 5) + (rg & 3);
-                    stage[((ROLE * G + u) << 10) + row * 32 + (lane & 31)] = acc[t - T0][rg];
-                }
+                for (int rq = 0; rq < 4; ++rq)
+                    stage[((ROLE * G + u) * 4 + rq) * 64 + lane] =
+                        v4i{acc[t - T0][4 * rq], acc[t - T0][4 * rq + 1], acc[t - T0][4 * rq + 2],
+                            acc[t - T0][4 * rq + 3]};
             }
         }
         __syncthreads();
+        const int NQ = (NT - t0 < G ? NT - t0 : G) * 256;   // (tile, rq, lane) quads this round
 #pragma unroll
-        for (int u = 0; u < G; ++u) {
+        for (int qq = tid; qq < NQ; qq += kMfmaThreads) {
+            const int u = qq >> 8, rq = (qq >> 6) & 3, ln = qq & 63;
             const int t = t0 + u;
-            if (t < NT) {
-                const int I = tile_I(D, TRI, t);
-                const int J = tile_J(D, TRI, t);
+            const int I = TRI ? tri_I_rt(t) : t / D;
+            const int J = TRI ? tri_J_rt(t) : t % D;
+            const int i0 = (row_blk + I) * 32 + 8 * rq + 4 * (ln >> 5);
+            const int j = (col_blk + J) * 32 + (ln & 31);
+            const int e = (u * 4 + rq) * 64 + ln;
+            const v4i rr = stage[(kRR * G * 4) * 64 + e];
+            const v4i ii = stage[(kII * G * 4) * 64 + e];
+            const v4i ir = stage[(kIR * G * 4) * 64 + e];
+            const v4i ri = stage[(kRI * G * 4) * 64 + e];
+            int64_t p = (int64_t)i0 * (i0 + 1) / 2 + j;
 #pragma unroll
-                for (int k = 0; k < 1024 / kMfmaThreads; ++k) {
-                    const int e = tid + kMfmaThreads * k;
-                    const int i = (row_blk + I) * 32 + (e >> 5);
-                    const int j = (col_blk + J) * 32 + (e & 31);
-                    if (i < N && j <= i) {
-                        const int rr = stage[((kRR * G + u) << 10) + e];
-                        const int ii = stage[((kII * G + u) << 10) + e];
-                        const int ir = stage[((kIR * G + u) << 10) + e];
-                        const int ri = stage[((kRI * G + u) << 10) + e];
-                        int re = (rr >> 8) + (ii >> 8);
-                        int im = (ir >> 8) - (ri >> 8);
-                        int2 *dst = out_f + (int64_t)i * (i + 1) / 2 + j;
-                        if (accumulate) {
-                            const int2 o = *dst;
-                            re += o.x;
-                            im += o.y;
-                        }
-                        *dst = make_int2(re, im);
+            for (int m = 0; m < 4; ++m) {
+                const int i = i0 + m;
+                if (i < N && j <= i) {
+                    int re = (rr[m] >> 8) + (ii[m] >> 8);
+                    int im = (ir[m] >> 8) - (ri[m] >> 8);
+                    if (accumulate) {
+                        const int2 o = out_f[p];
+                        re += o.x;
+                        im += o.y;
                     }
+                    out_f[p] = make_int2(re, im);
                 }
+                p += i + 1;
             }
         }
         __syncthreads();
@@ -473,7 +519,7 @@ __device__ __forceinline__ void mfma4_dispatch(uint8_t *smem, const uint8_t *__r
 #define XC_CASE(W)                                                                                  \
     case W:                                                                                         \
         mfma4_region<D, TRI, KC, NBUF, VEC, ((W) & 3), ((W) >> 2)>(smem, volts, T, F, N, f, row_blk,   \
-                                                             col_blk, acc_out, accumulate);        \
+                                                                 col_blk, acc_out, accumulate);    \
         break;
         XC_CASE(0) XC_CASE(1) XC_CASE(2) XC_CASE(3) XC_CASE(4) XC_CASE(5) XC_CASE(6) XC_CASE(7)
 #undef XC_CASE
@@ -481,21 +527,18 @@ __device__ __forceinline__ void mfma4_dispatch(uint8_t *smem, const uint8_t *__r
     }
 }
 
-constexpr int kNBuf = 6;
-
 // One work-group per (channel, region).  Regions of one channel: nseg
 // triangles on the diagonal segments, then the nseg(nseg-1)/2 rectangles
 // (a, b), a > b, in row-major order.  Segments are D blocks each (the input
 // count is zero-padded up to 32*D*nseg).
 template <int D, int KC, int VEC>
-__global__ __launch_bounds__(kMfmaThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
+__global__ __launch_bounds__(kMfmaThreads)
+__attribute__((amdgpu_waves_per_eu(2 * mfma4_wgs_per_cu(D), 2 * mfma4_wgs_per_cu(D))))
 void xc_mfma4_kernel(const uint8_t *__restrict__ volts, int64_t T, int F, int N, int nseg, int R,
                      int nitems, int2 *__restrict__ acc_out, int accumulate)
 {
-    constexpr int RING = kNBuf * KC * kRowBytes;
-    constexpr int STAGE = 4 * 4 * 1024 * 4;
-    constexpr int SMEM = RING > STAGE ? RING : STAGE;
-    __shared__ __attribute__((aligned(1024))) uint8_t smem[SMEM];
+    constexpr int NBUF = mfma4_nbuf(D, KC);
+    __shared__ __attribute__((aligned(1024))) uint8_t smem[mfma4_smem_bytes(D, KC)];
 
     const int item = xcd_item();
     if (item >= nitems)
@@ -503,7 +546,7 @@ void xc_mfma4_kernel(const uint8_t *__restrict__ volts, int64_t T, int F, int N,
     const int f = item / R;
     const int r = item - f * R;
     if (r < nseg) {
-        mfma4_dispatch<D, true, KC, kNBuf, VEC>(smem, volts, T, F, N, f, r * D, r * D, acc_out, accumulate);
+        mfma4_dispatch<D, true, KC, NBUF, VEC>(smem, volts, T, F, N, f, r * D, r * D, acc_out, accumulate);
     } else if constexpr (D <= 4) {
         const int k = r - nseg;
         int a = (int)((1.f + sqrtf(1.f + 8.f * k)) * 0.5f);
@@ -512,8 +555,8 @@ void xc_mfma4_kernel(const uint8_t *__restrict__ volts, int64_t T, int F, int N,
         while ((a + 1) * a / 2 <= k)
             ++a;
         const int b = k - a * (a - 1) / 2;
-        mfma4_dispatch<D, false, KC, kNBuf, VEC>(smem, volts, T, F, N, f, a * D, b * D, acc_out,
-                                                 accumulate);
+        mfma4_dispatch<D, false, KC, NBUF, VEC>(smem, volts, T, F, N, f, a * D, b * D, acc_out,
+                                                accumulate);
     }
 }
 
@@ -584,18 +627,25 @@ static hipError_t launch_mfma4_t(const Plan &pl, const uint8_t *volts, int64_t T
     // the LDS-DMA path addresses one chunk of KC time rows with 32-bit offsets
     const int vec_ok = (N % 16 == 0) && ((uintptr_t)volts % 16 == 0) &&
                        (int64_t)KC * F * N < (1LL << 31) - 16;
-    dim3 grid(xcd_grid(nitems)), block(kMfmaThreads);
     auto kern = vec_ok ? xc_mfma4_kernel<D, KC, 1> : xc_mfma4_kernel<D, KC, 0>;
-    hipLaunchKernelGGL(kern, grid, block, 0, s, volts, T, F, N, pl.nseg, pl.regions, nitems, acc,
-                       accumulate);
+    hipLaunchKernelGGL(kern, dim3(xcd_grid(nitems)), dim3(kMfmaThreads), 0, s, volts, T, F, N,
+                       pl.nseg, pl.regions, nitems, acc, accumulate);
     return hipGetLastError();
 }
 
 hipError_t launch_mfma4(const Plan &pl, int kc, const uint8_t *volts, int64_t T, int F, int N,
                         int2 *acc, int accumulate, hipStream_t s)
 {
-    if (kc != 64 || !plan_supported(N, pl.D))
+    if ((kc != 64 && kc != 128) || !plan_supported(N, pl.D))
         return hipErrorInvalidValue;
+    if (kc == 128) {
+        switch (pl.D) {
+        case 4: return launch_mfma4_t<4, 128>(pl, volts, T, F, N, acc, accumulate, s);
+        case 5: return launch_mfma4_t<5, 128>(pl, volts, T, F, N, acc, accumulate, s);
+        case 6: return launch_mfma4_t<6, 128>(pl, volts, T, F, N, acc, accumulate, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
     switch (pl.D) {
     case 1: return launch_mfma4_t<1, 64>(pl, volts, T, F, N, acc, accumulate, s);
     case 2: return launch_mfma4_t<2, 64>(pl, volts, T, F, N, acc, accumulate, s);

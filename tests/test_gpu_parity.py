@@ -192,3 +192,20 @@ def test_tianlai_full_size_sampled():
     assert not om[:, autos, 1].any() and (om[:, autos, 0] >= 0).all()
     m.close()
     p.close()
+
+
+PERSIST = [(256, 300, 4), (96, 700, 3), (64, 1100, 2), (192, 700, 6), (512, 40, 4), (130, 500, 2)]
+
+
+@pytest.mark.parametrize("N,F,tile", PERSIST, ids=[f"N{n}F{f}D{d}" for n, f, d in PERSIST])
+def test_persistent_workgroups_walk_many_regions(N, F, tile):
+    """More (channel, region) items than resident work-groups: each work-group
+    walks several items, mixing triangles and rectangles; every channel is
+    checked on a sample of channels against the oracle."""
+    T = 96
+    _say(f"persistent N={N} F={F} D={tile}")
+    v = synth.uniform_volts4(N, F, T, seed=(1006, N, F))
+    got = gpu_correlate(v, N, F, 4, X.PATH_I8_MFMA, tile)
+    chans = sorted(set([0, 1, F // 3, F // 2, F - 2, F - 1]))
+    ref = oracle.to_int32(oracle.xcorr(v.numpy(), 4, T, F, N, chans=chans))
+    assert np.array_equal(got[chans], ref)
