@@ -3,7 +3,7 @@
  *
  * The X-engine of an FX correlator receives channelised voltages and, per
  * frequency channel, forms the conjugate multiply-accumulate (CMAC) of every
- * input pair over an integration (paper: Section 2.4 "X-engine"; Eq. 2 of
+ * input pair over an integration (paper: Section 2.3 "X-engine"; Eq. 2 of
  * Section 3.2 defines a visibility as the time average of S1* . S2).  This
  * library computes, for each channel f and each pair j <= i of the N inputs,
  *
@@ -13,7 +13,7 @@
  * p = i(i+1)/2 + j; autos are included, so P = N(N+1)/2 pairs per channel.
  *
  * Input formats (Section 2.1 "F-engine": 4-bit real + 4-bit imaginary after
- * requantisation; Section 2.4: the fluff step widens them to 8+8 bits):
+ * requantisation; Section 2.3: the fluff step widens them to 8+8 bits):
  *   sample_bits = 4 : uint8 per sample, high nibble = real, low nibble =
  *                     imaginary, two's complement in [-8, 7].
  *   sample_bits = 8 : int8 real then int8 imaginary, each in [-127, 127]
@@ -74,9 +74,10 @@ typedef struct {
     int32_t sample_bits;  /* 4 or 8 */
     int32_t path;         /* XCORR_PATH_* */
     int32_t layout;       /* XCORR_LAYOUT_TFN */
-    int32_t tile;         /* MFMA paths: diagonal block size in 32-input blocks
-                             (2, 3, 4 or 6); 0 = tuned value from the tune
-                             cache, else a built-in choice */
+    int32_t tile;         /* MFMA paths: diagonal block size D in 32-input
+                             blocks: 2..4 for any N (1 only when N <= 32),
+                             5 or 6 only when N <= 32*D; 0 = tuned value from
+                             the tune cache, else a built-in choice */
     int64_t max_samples_per_dump; /* 0 = the format's T_max; larger than
                                      T_max is XCORR_E_OVERFLOW */
 } xcorr_config;
@@ -101,7 +102,7 @@ typedef struct {
  *   t_max           : largest integration, in samples, that stays exact
  * Any output pointer may be NULL.  Errors: XCORR_E_INVAL for an invalid
  * config (N < 1, F < 1, bits not 4/8, unknown path or layout, FP16 path with
- * 4-bit input, tile not in {0,2,3,4,6}); XCORR_E_OVERFLOW if
+ * 4-bit input, unsupported tile); XCORR_E_OVERFLOW if
  * max_samples_per_dump > t_max.
  */
 int xcorr_query(const xcorr_config *cfg, size_t *workspace_bytes, size_t *out_bytes, int64_t *t_max);

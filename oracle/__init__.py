@@ -10,7 +10,7 @@ marshals numpy arrays through ctypes, plus the int32 range check that the
 integer result must pass (the GPU path accumulates in int32 and must refuse,
 not wrap, past that bound).
 
-Definition followed (paper, Section 2.4 "X-engine" and Eq. 2 of Section 3.2):
+Definition followed (paper, Section 2.3 "X-engine" and Eq. 2 of Section 3.2):
 for each channel f and each pair j <= i,
     V_ij[f] = sum_t x_i[f,t] * conj(x_j[f,t]),
 stored at pair index p = i(i+1)/2 + j as (re, im).

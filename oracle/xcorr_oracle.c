@@ -6,7 +6,7 @@
  * smoke check and the CPU-baseline leg of the benchmark may load it.  It
  * shares no code, header, table or helper with the GPU library.
  *
- * What it computes (paper: Section 2.4 "X-engine" defines the X-engine as the
+ * What it computes (paper: Section 2.3 "X-engine" defines the X-engine as the
  * conjugate multiplication and accumulation of channelised voltages; Eq. 2 in
  * Section 3.2 "Phase testing" defines a visibility as the time average of
  * S1* . S2):
@@ -21,7 +21,7 @@
  * S1 = x_j and S2 = x_i.
  *
  * Input formats (Section 2.1 "F-engine": the channelised data are truncated
- * to 4-bit real + 4-bit imaginary; Section 2.4: the fluff step widens them to
+ * to 4-bit real + 4-bit imaginary; Section 2.3: the fluff step widens them to
  * 8-bit + 8-bit):
  *   bits = 4 : one byte per (t, f, input); high nibble = real part, low
  *              nibble = imaginary part, each 4-bit two's complement [-8, 7].

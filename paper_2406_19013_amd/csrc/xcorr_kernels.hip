@@ -1,7 +1,7 @@
 // gfx950 kernels of the X-engine cross-multiply-accumulate.
 //
 // For every channel f and pair j <= i:  V_ij = sum_t x_i[t] * conj(x_j[t])
-// (paper Section 2.4 "X-engine"; Eq. 2 of Section 3.2), i.e. per channel the
+// (paper Section 2.3 "X-engine"; Eq. 2 of Section 3.2), i.e. per channel the
 // lower triangle of the Hermitian rank-T update X X^H, accumulated in int32.
 //
 //   xc_plain_kernel   VALU int32 multiply-adds (the comparison path)

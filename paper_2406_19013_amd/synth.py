@@ -6,7 +6,7 @@ holds none of the correlation arithmetic, so both the GPU library's tests and
 the CPU oracle can be fed from it.
 
 Formats (paper Section 2.1 "F-engine": channel data are truncated to a 4-bit
-real and a 4-bit imaginary part; Section 2.4: the fluff step widens them to
+real and a 4-bit imaginary part; Section 2.3: the fluff step widens them to
 8-bit + 8-bit):
 
 * 4+4-bit: one uint8 per (t, f, input), high nibble = real, low nibble =
