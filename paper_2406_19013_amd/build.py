@@ -2,11 +2,16 @@
 
     python -m paper_2406_19013_amd.build [--verbose]
 
-Every call compiles; the library is written next to this file.
+Every call compiles; the library is written next to this file.  The
+compiler's per-kernel resource report (registers, scratch, occupancy, LDS) is
+written to _build/kernel_resources.txt; a kernel that spills registers to
+scratch is named on stderr.
 """
 from __future__ import annotations
 
+import concurrent.futures as cf
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -18,7 +23,12 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libxcorr.so")
 ARCH = "gfx950"
 
-SOURCES = ["xcorr_kernels.hip", "xcorr_api.cpp"]
+# (source, extra flags, object name).  The 8+8-bit MFMA kernels are compiled
+# once per diagonal block size so that the objects build in parallel.
+UNITS = [("xcorr_kernels.hip", [], "xcorr_kernels.o"), ("xcorr_api.cpp", [], "xcorr_api.o"),
+         ("xcorr_mfma4.hip", [], "xcorr_mfma4.o")] + [
+    ("xcorr_mfma8.hip", [f"-DXC_D={d}"], f"xcorr_mfma8_d{d}.o") for d in range(1, 7)]
+RESOURCES = "kernel_resources.txt"
 
 # Packed FP32 VALU ops are disabled for every device compile.
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
@@ -33,26 +43,68 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+_REMARK = re.compile(r"remark:\s+(Function Name|VGPRs|AGPRs|ScratchSize \[bytes/lane\]|Occupancy \[waves/SIMD\]"
+                     r"|LDS Size \[bytes/block\]): (\S+)")
+
+
 def _run(cmd, verbose):
+    """Run one compiler step; return its kernel resource remarks as
+    [(kernel, {field: value})]."""
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
-    out = "\n".join(l for l in r.stdout.splitlines() if "packed-fp32-ops" not in l)
+    kernels, rest = [], []
+    for line in r.stdout.splitlines():
+        m = _REMARK.search(line)
+        if m:
+            if m.group(1) == "Function Name":
+                kernels.append((m.group(2), {}))
+            elif kernels:
+                kernels[-1][1][m.group(1).split(" ")[0]] = m.group(2)
+        elif "packed-fp32-ops" not in line and "kernel-resource-usage" not in line:
+            rest.append(line)
+    out = "\n".join(rest)
     if r.returncode != 0:
         raise RuntimeError(f"build step failed ({r.returncode}):\n{' '.join(cmd)}\n{out}")
     if verbose and out.strip():
         print(out)
+    return kernels
 
 
-def build(verbose: bool = False) -> str:
+def read_resources(path: str | None = None) -> dict:
+    """{kernel symbol: {"VGPRs", "AGPRs", "ScratchSize", "Occupancy", "LDS": int}}
+    from the report of the last build."""
+    path = path or os.path.join(HERE, "_build", RESOURCES)
+    res = {}
+    with open(path) as fh:
+        for line in fh:
+            parts = line.split()
+            if len(parts) >= 2 and not line.startswith("#"):
+                res[parts[0]] = {k: int(v) for k, v in (f.split("=") for f in parts[1:])}
+    return res
+
+
+def build(verbose: bool = False, jobs: int | None = None) -> str:
     cc = hipcc()
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
-    objs = []
-    for src in SOURCES:
-        obj = os.path.join(bdir, src + ".o")
-        _run([cc, *COMMON, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
-        objs.append(obj)
+    objs = [os.path.join(bdir, o) for _, _, o in UNITS]
+    cmds = [[cc, *COMMON, *flags, "-Rpass-analysis=kernel-resource-usage", "-c",
+             os.path.join(CSRC, src), "-o", obj]
+            for (src, flags, _), obj in zip(UNITS, objs)]
+    jobs = jobs or min(len(cmds), max(1, min(16, os.cpu_count() or 1)))
+    with cf.ThreadPoolExecutor(jobs) as ex:
+        reports = list(ex.map(lambda c: _run(c, verbose), cmds))
+    with open(os.path.join(bdir, RESOURCES), "w") as fh:
+        fh.write("# kernel VGPRs AGPRs ScratchSize(bytes/lane) Occupancy(waves/SIMD) LDS(bytes)\n")
+        for kernels in reports:
+            for name, f in kernels:
+                fields = " ".join(f"{k}={f[k]}" for k in ("VGPRs", "AGPRs", "ScratchSize", "Occupancy", "LDS")
+                                  if k in f)
+                fh.write(f"{name} {fields}\n")
+                if int(f.get("ScratchSize", "0")):
+                    print(f"build: kernel {name} spills {f['ScratchSize']} bytes/lane to scratch",
+                          file=sys.stderr)
     tmp = LIB + ".tmp%d" % os.getpid()
     _run([cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
     os.replace(tmp, LIB)

@@ -97,8 +97,6 @@ int validate(const xcorr_config *c, int64_t *t_max_out)
         return set_error(XCORR_E_INVAL, "unknown path");
     if (c->path == XCORR_PATH_F16_MFMA && c->sample_bits != 8)
         return set_error(XCORR_E_INVAL, "the FP16 path takes 8+8-bit input only");
-    if (c->path == XCORR_PATH_F16_MFMA || (c->path == XCORR_PATH_I8_MFMA && c->sample_bits == 8))
-        return set_error(XCORR_E_INVAL, "path not built in this library version");
     if (c->tile != 0 && !xc::plan_supported(c->n_inputs, c->tile))
         return set_error(XCORR_E_INVAL, "tile must be 0, 2, 3, 4, or 6 (6 only for N <= 192)");
     const int64_t tmax = c->sample_bits == 4 ? XCORR_TMAX_4BIT : XCORR_TMAX_8BIT;
@@ -165,14 +163,14 @@ int xcorr_init(const xcorr_config *cfg, void *d_workspace, size_t ws_bytes, xcor
     c->t_max = tm;
     c->max_dump = cfg->max_samples_per_dump ? cfg->max_samples_per_dump : tm;
     c->kc = 64;
-    if (cfg->path == XCORR_PATH_I8_MFMA) {
+    if (cfg->path != XCORR_PATH_PLAIN) {
         int tile = cfg->tile ? cfg->tile : cached_tile(*cfg);
         if (!tile)
             tile = default_tile(cfg->n_inputs);
         c->plan = xc::make_plan(cfg->n_inputs, tile);
         // time rows staged per LDS chunk (64 or 128; 128 for D >= 4 only)
         const char *v = std::getenv("XCORR_CHUNK");
-        if (v && std::strcmp(v, "128") == 0 && c->plan.D >= 4)
+        if (v && std::strcmp(v, "128") == 0 && c->plan.D >= 4 && cfg->sample_bits == 4)
             c->kc = 128;
     }
     c->ws = d_workspace;
@@ -204,8 +202,11 @@ int xcorr_ingest(xcorr_ctx *ctx, const void *d_volts, int64_t n_samples, uint64_
         hipError_t e;
         if (c.path == XCORR_PATH_PLAIN)
             e = xc::launch_plain(c.sample_bits, vp, tl, c.n_chans, c.n_inputs, acc, accumulate, s);
-        else
+        else if (c.sample_bits == 4)
             e = xc::launch_mfma4(ctx->plan, ctx->kc, vp, tl, c.n_chans, c.n_inputs, acc, accumulate, s);
+        else
+            e = xc::launch_mfma8(ctx->plan, c.path == XCORR_PATH_F16_MFMA, vp, tl, c.n_chans, c.n_inputs,
+                                 ctx->ws, accumulate, s);
         if (e != hipSuccess)
             return hip_fail(e, "kernel launch");
         ++ctx->launches;

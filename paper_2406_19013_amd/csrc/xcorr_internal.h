@@ -30,6 +30,24 @@ hipError_t launch_plain(int bits, const uint8_t *volts, int64_t T, int F, int N,
                         int accumulate, hipStream_t s);
 hipError_t launch_mfma4(const Plan &pl, int kc, const uint8_t *volts, int64_t T, int F, int N,
                         int2 *acc, int accumulate, hipStream_t s);
+// 8+8-bit input, int8 MFMA (f16 = false, int2 accumulators) or FP16 MFMA with
+// FP32 accumulation (f16 = true, float2 accumulators).
+hipError_t launch_mfma8(const Plan &pl, bool f16, const uint8_t *volts, int64_t T, int F, int N, void *acc,
+                        int accumulate, hipStream_t s);
+// per-D launchers of the 8+8-bit kernels (xcorr_mfma8.hip compiled with -DXC_D=d)
+hipError_t launch_mfma8_d1(const Plan &pl, bool f16, const uint8_t *volts, int64_t T, int F, int N,
+                          void *acc, int accumulate, hipStream_t s);
+hipError_t launch_mfma8_d2(const Plan &pl, bool f16, const uint8_t *volts, int64_t T, int F, int N,
+                          void *acc, int accumulate, hipStream_t s);
+hipError_t launch_mfma8_d3(const Plan &pl, bool f16, const uint8_t *volts, int64_t T, int F, int N,
+                          void *acc, int accumulate, hipStream_t s);
+hipError_t launch_mfma8_d4(const Plan &pl, bool f16, const uint8_t *volts, int64_t T, int F, int N,
+                          void *acc, int accumulate, hipStream_t s);
+hipError_t launch_mfma8_d5(const Plan &pl, bool f16, const uint8_t *volts, int64_t T, int F, int N,
+                          void *acc, int accumulate, hipStream_t s);
+hipError_t launch_mfma8_d6(const Plan &pl, bool f16, const uint8_t *volts, int64_t T, int F, int N,
+                          void *acc, int accumulate, hipStream_t s);
+
 hipError_t launch_dump(const void *acc, void *out, int64_t bytes, int empty, hipStream_t s);
 
 }  // namespace xc
