@@ -139,6 +139,56 @@ int xcorr_dump(xcorr_ctx *ctx, void *d_out, int64_t *n_integrated, uint64_t *n_g
 
 int xcorr_stats(const xcorr_ctx *ctx, xcorr_stats_t *out);
 int xcorr_destroy(xcorr_ctx *ctx);
+
+/*
+ * Batched persistent launch (4+4-bit, int8-MFMA contexts only).  The X-engine
+ * of Section 2.3 runs once per array; a batch correlates up to
+ * XCORR_MAX_BATCH arrays of uneven N, F and sample count in one kernel that
+ * drains a work queue of (array, channel, region) items.  Results, the
+ * integration bookkeeping and the dumps stay per context (xcorr_dump).
+ *
+ * xcorr_batch_query: device bytes the batch needs (its work-queue counters).
+ * xcorr_batch_init : ctxs[0..n) are borrowed (they must outlive the batch and
+ *   keep their workspaces); d_workspace (>= the queried size, 256-byte
+ *   aligned) is borrowed until xcorr_batch_destroy and is initialised here
+ *   with a synchronous kernel on the null stream.  Each array keeps its own
+ *   region plan when its tile is 2, 3 or 4; other tiles are replaced by
+ *   whichever of 2, 3, 4 pads least (xcorr_batch_tiles reports the choice).
+ *   Errors: XCORR_E_INVAL (n outside 1..XCORR_MAX_BATCH, a NULL or repeated
+ *   context, a context that is not 4-bit int8-MFMA), XCORR_E_NOMEM, XCORR_E_HIP.
+ * xcorr_batch_ingest: d_volts[a] = [n_samples[a]][F_a][N_a] for array a;
+ *   n_samples[a] = 0 leaves array a out of this ingest.  seqs may be NULL (each
+ *   array's sequence then continues without a gap).  Checks, before anything
+ *   is enqueued: XCORR_E_INVAL (NULL arrays, negative counts, all counts 0),
+ *   XCORR_E_OVERFLOW if any array would pass its max_samples_per_dump.  Every
+ *   launch leaves the queue counters as it found them, so an ingest can be
+ *   captured in a HIP graph and replayed; a replay repeats the overwrite /
+ *   accumulate choice made at capture, so capture whole integrations (the
+ *   first ingest after a dump through the dump).  Launches of one batch must
+ *   not overlap (one stream at a time).
+ */
+#define XCORR_MAX_BATCH 16
+int xcorr_batch_query(xcorr_ctx *const *ctxs, int n, size_t *workspace_bytes);
+int xcorr_batch_init(xcorr_ctx *const *ctxs, int n, void *d_workspace, size_t ws_bytes, xcorr_batch **out);
+int xcorr_batch_ingest(xcorr_batch *b, const void *const *d_volts, const int64_t *n_samples,
+                       const uint64_t *seqs, void *stream);
+int xcorr_batch_tiles(const xcorr_batch *b, int32_t *tiles);
+int xcorr_batch_destroy(xcorr_batch *b);
+
+/*
+ * Autotuner: times every supported tile of an MFMA-path config on a
+ * synthetic block of 2048 samples (a fixed hash pattern written into the
+ * scratch) and returns the fastest in *best_tile; when $XCORR_TUNE_CACHE
+ * names a file, the line "bits N F path tile" is appended to it, and
+ * xcorr_init with tile = 0 then uses the last matching line.  The call
+ * blocks until the timing runs on `stream` have finished.
+ * xcorr_autotune_query gives the scratch size (accumulators + input block).
+ * Errors: as xcorr_query, XCORR_E_INVAL for the plain path or a NULL
+ * best_tile, XCORR_E_NOMEM for missing or short scratch, XCORR_E_HIP.
+ */
+int xcorr_autotune_query(const xcorr_config *cfg, size_t *scratch_bytes);
+int xcorr_autotune(const xcorr_config *cfg, void *d_scratch, size_t scratch_bytes, void *stream,
+                   int32_t *best_tile);
 const char *xcorr_strerror(int code);
 /* Detail of the last XCORR_E_HIP / XCORR_E_DEVICE on this thread. */
 const char *xcorr_last_error(void);

@@ -1,0 +1,299 @@
+// Device code of the 4+4-bit int8-MFMA path: one work-group body per region
+// shape and wave.  Included by the single-array kernels (xcorr_mfma4.hip) and
+// the batched persistent kernel (xcorr_batch.hip).
+#pragma once
+#include "xc_mfma.h"
+
+namespace xc {
+namespace {
+
+// ---------------------------------------------------------------------------
+// 4+4-bit int8-MFMA path.
+//
+// Per channel the packed voltages form a matrix X[i][t] (one byte per sample).
+// With R = 16*re and Im16 = 16*im as int8 (a nibble moved to the high half of
+// a byte is 16x its value, exact), the four real products
+//     RR = R R^T, II = Im16 Im16^T, IR = Im16 R^T, RI = R Im16^T
+// give 256*Re V = RR + II and 256*Im V = IR - RI on every 32x32 tile.  Each
+// of the four waves of a work-group computes one of the four products for
+// every tile of its region, so the waves carry identical MFMA counts for any
+// region shape.  Raw packed bytes are staged in LDS in their HBM order
+// [t][inputs]; ds_read_b64_tr_b8 turns 8 time rows x 16 inputs into the
+// per-lane [input][8 samples] MFMA operand layout, and two masks unpack it.
+//
+// v_mfma_i32_32x32x32_i8 operand layout (gfx950): lane l supplies row l%32,
+// k-half l/32, 16 int8; result register r of lane l is row 8(r/4) + 4(l/32) +
+// r%4, column l%32.
+
+// Two transposing 8-byte reads, 8 time rows apart: the lane's 16 samples of
+// one input.  `p` is an LDS address; the row offsets fold into the
+// instructions' immediate offsets.
+template <int EIGHT_ROWS>
+__device__ __forceinline__ v4i frag_tr8(lds_u8 *p)
+{
+    const v2i lo = __builtin_amdgcn_ds_read_tr8_b64_v2i32((lds_v2i *)p);
+    const v2i hi = __builtin_amdgcn_ds_read_tr8_b64_v2i32((lds_v2i *)(p + EIGHT_ROWS));
+    return v4i{lo.x, lo.y, hi.x, hi.y};
+}
+
+// Wave roles: which real product a wave accumulates.  A role fixes the nibble
+// of its row (A) and column (B) operands: 0 = real part, 4 = imaginary part.
+enum Role { kRR = 0, kII = 1, kIR = 2, kRI = 3 };
+constexpr int role_shift_a(int role) { return (role == kII || role == kIR) ? 4 : 0; }
+constexpr int role_shift_b(int role) { return (role == kII || role == kRI) ? 4 : 0; }
+
+// A nibble moved into the high half of a byte reads as 16x its value: the
+// real part is x & 0xF0, the imaginary part (x << 4) & 0xF0, both exact int8.
+__device__ __forceinline__ v4i re16(v4i x) { return x & (int)0xF0F0F0F0; }
+__device__ __forceinline__ v4i im16(v4i x) { return (x << 4) & (int)0xF0F0F0F0; }
+
+// LDS layout of one staged chunk: KC time rows of 256 bytes, i.e. 16 units of
+// 16 bytes.  Unit p of a row holds inputs 16p..16p+15 of the region (units
+// 0..2D-1: row blocks, 2D..4D-1: column blocks of a rectangle).  Unit p of row
+// r is stored at position p ^ ((r & 7) << 1), so that the 8 rows x 2 units a
+// transpose-read of two 16-lane groups touches fall on 16 distinct positions
+// (64 distinct banks).
+constexpr int kRowBytes = 256;
+
+// One 32-sample K step of one wave: read each LDS block the wave's tiles
+// touch once (two transpose reads), unpack the nibble(s) its role needs, and
+// issue its tiles' MFMAs.  addr[b] = this lane's LDS address of block b in the
+// current chunk; KOFF = the K step's row offset.
+template <int D, bool TRI, int ROLE, int HALF, int KOFF>
+__device__ __forceinline__ void k_step(lds_u8 *const *addr, v16i *acc)
+{
+    constexpr int NB = TRI ? D : 2 * D;
+    constexpr int T0 = half_begin(D, TRI, HALF), T1 = half_end(D, TRI, HALF);
+    constexpr int SA = role_shift_a(ROLE), SB = role_shift_b(ROLE);
+    v4i A[NB], B[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const bool ua = half_uses_row(D, TRI, HALF, b), ub = half_uses_col(D, TRI, HALF, b);
+        if (ua || ub) {
+            const v4i x = frag_tr8<8 * kRowBytes>(addr[b] + KOFF);
+            if (ua)
+                A[b] = SA ? im16(x) : re16(x);
+            if (ub)
+                B[b] = (ua && SA == SB) ? A[b] : (SB ? im16(x) : re16(x));
+        }
+    }
+#pragma unroll
+    for (int t = T0; t < T1; ++t)
+        acc[t - T0] = mfma_i8(A[row_block(D, TRI, t)], B[col_block(D, TRI, t)], acc[t - T0]);
+}
+
+
+
+// Occupancy plan: regions of D <= 3 blocks fit 128 registers per wave, so two
+// work-groups share a CU (their barriers are independent, which hides LDS
+// latency); larger regions take the CU alone.  LDS per work-group holds the
+// ring of NBUF packed chunks; after the main loop it is reused as the
+// epilogue stage of G tiles x 4 products x 4 KB.
+constexpr int mfma4_wgs_per_cu(int D) { return D <= 3 ? 2 : 1; }
+constexpr int mfma4_nbuf(int D, int KC) { return D <= 3 ? 4 : (KC == 64 ? 6 : 3); }
+constexpr int mfma4_epilogue_tiles(int D) { return D <= 3 ? 4 : 7; }
+constexpr int mfma4_smem_bytes(int D, int KC)
+{
+    return mfma4_nbuf(D, KC) * KC * kRowBytes > mfma4_epilogue_tiles(D) * 16384
+               ? mfma4_nbuf(D, KC) * KC * kRowBytes
+               : mfma4_epilogue_tiles(D) * 16384;
+}
+
+// Whole work-group body for one region shape and one wave (role, half).
+// row_blk / col_blk: first 32-input block of the region's rows / columns.
+//
+// VEC = 1 (N a multiple of 16, 16-byte aligned input): chunks of KC time rows
+// go HBM -> LDS by buffer_load_dwordx4 ... lds into a ring of NBUF buffers,
+// NBUF-1 chunks ahead of the MFMAs; the buffer descriptor of each chunk ends at
+// the last valid time row, and inputs >= N use an out-of-range offset, so the
+// hardware supplies the zero padding.  VEC = 0: each chunk is staged through
+// registers, with byte loads for the ragged row end.
+template <int D, bool TRI, int KC, int NBUF, int VEC, int ROLE, int HALF>
+__device__ __forceinline__ void mfma4_region(uint8_t *smem, const uint8_t *__restrict__ volts,
+                                             int64_t T, int F, int N, int f, int row_blk, int col_blk,
+                                             int2 *__restrict__ acc_out, int accumulate)
+{
+    constexpr int NT = n_tiles(D, TRI);
+    constexpr int T0 = half_begin(D, TRI, HALF), T1 = half_end(D, TRI, HALF);
+    constexpr int NB = TRI ? D : 2 * D;                 // 32-input blocks staged per row
+    constexpr int BUF = KC * kRowBytes;
+    constexpr int LOADS = KC * 16 / kMfmaThreads;       // 16-byte units per thread per chunk
+    constexpr int G = mfma4_epilogue_tiles(D);          // tiles per epilogue round
+    static_assert(LOADS * kMfmaThreads == KC * 16, "chunk must be a whole number of wave loads");
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int g = lane >> 4, q = lane & 15;
+    lds_u8 *const ring = (lds_u8 *)smem;
+
+    // operand read offsets: row (g>>1)*16 + q>>1 of the K step, unit 2b + (g&1)
+    const int row_off = ((g >> 1) * 16 + (q >> 1)) * kRowBytes + (q & 1) * 8;
+    int colo[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+        colo[b] = ((2 * b + (g & 1)) ^ (q & 14)) << 4;
+
+    // fill slots: unit U = (wave*LOADS + k)*64 + lane -> row U/16, position U%16
+    const int64_t row_bytes = (int64_t)F * N;
+    int voff[LOADS];
+#pragma unroll
+    for (int k = 0; k < LOADS; ++k) {
+        const int U = (wave * LOADS + k) * 64 + lane;
+        const int r = U >> 4;
+        const int p = (U & 15) ^ ((r & 7) << 1);
+        const int i0 = p < 2 * D ? row_blk * 32 + 16 * p : col_blk * 32 + 16 * (p - 2 * D);
+        const bool valid = p < 2 * NB && i0 < N;
+        voff[k] = valid ? (int)(r * row_bytes + (int64_t)f * N + i0) : kBufferOutOfRange;
+    }
+
+    v16i acc[T1 > T0 ? T1 - T0 : 1];   // a half may own no tile (D = 1)
+#pragma unroll
+    for (int t = 0; t < (T1 > T0 ? T1 - T0 : 1); ++t)
+        acc[t] = v16i{};
+
+    const int nchunks = (int)((T + KC - 1) / KC);
+    auto issue = [&](int c, int bufi) {
+        const int64_t rows = min((int64_t)KC, T - (int64_t)c * KC);
+        __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(volts + (int64_t)c * KC * row_bytes), (short)0, (int)(rows * row_bytes), 0x00020000);
+        lds_u8 *dst = ring + bufi * BUF + wave * LOADS * 1024;
+#pragma unroll
+        for (int k = 0; k < LOADS; ++k)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (__attribute__((address_space(3))) void *)(dst + k * 1024),
+                                                     16, voff[k], 0, 0, 0);
+    };
+    auto fill_sync = [&](int c, int bufi) {
+        lds_u8 *dst = ring + bufi * BUF;
+#pragma unroll
+        for (int k = 0; k < LOADS; ++k) {
+            const int U = (wave * LOADS + k) * 64 + lane;
+            const int r = U >> 4;
+            const int p = (U & 15) ^ ((r & 7) << 1);
+            const int i0 = p < 2 * D ? row_blk * 32 + 16 * p : col_blk * 32 + 16 * (p - 2 * D);
+            const v4i val = p < 2 * NB ? load_piece(volts, (int64_t)c * KC + r, T, f, F, N, i0, 1, 0)
+                                       : v4i{0, 0, 0, 0};
+            *(__attribute__((address_space(3))) v4i *)(dst + U * 16) = val;
+        }
+    };
+
+    if constexpr (VEC) {
+#pragma unroll
+        for (int c = 0; c < NBUF - 1; ++c)
+            if (c < nchunks)
+                issue(c, c);
+    }
+    int bufc = 0;                 // ring slot of chunk c
+    for (int c = 0; c < nchunks; ++c) {
+        if constexpr (VEC) {
+            if (c + NBUF - 2 < nchunks)
+                wait_vmcnt<LOADS * (NBUF - 2)>();
+            else
+                wait_vmcnt<0>();
+            barrier_no_fence();   // chunk c is in LDS; every wave is done with chunk c-1
+            if (c + NBUF - 1 < nchunks)
+                issue(c + NBUF - 1, bufc == 0 ? NBUF - 1 : bufc - 1);   // the slot chunk c-1 used
+        } else {
+            __syncthreads();      // every wave is done with the slot being refilled
+            fill_sync(c, bufc);
+            __syncthreads();
+        }
+        lds_u8 *addr[NB];
+        lds_u8 *const cb = ring + bufc * BUF + row_off;
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+            addr[b] = cb + colo[b];
+#pragma unroll
+        for (int ks = 0; ks < KC / 32; ++ks) {
+            if (ks == 0)
+                k_step<D, TRI, ROLE, HALF, 0>(addr, acc);
+            else if (ks == 1)
+                k_step<D, TRI, ROLE, HALF, 32 * kRowBytes>(addr, acc);
+            else if (ks == 2)
+                k_step<D, TRI, ROLE, HALF, 64 * kRowBytes>(addr, acc);
+            else
+                k_step<D, TRI, ROLE, HALF, 96 * kRowBytes>(addr, acc);
+        }
+        bufc = bufc + 1 == NBUF ? 0 : bufc + 1;
+    }
+    __syncthreads();              // every wave is done with the ring
+
+    // Epilogue: the four roles' products of each tile meet in LDS, G tiles per
+    // round; 256*Re = RR + II and 256*Im = IR - RI (each a multiple of 256).
+    // Stage layout per (role, tile): [quad rq][lane][4] int32, so that a lane
+    // writes its registers 4..4rq+3 as one 16-byte store; result register r of
+    // lane l is row 8(r/4) + 4(l/32) + r%4, column l%32 of the tile.
+    typedef __attribute__((address_space(3))) v4i lds_v4i;
+    lds_v4i *const stage = (lds_v4i *)smem;
+    const int64_t P = (int64_t)N * (N + 1) / 2;
+    int2 *const out_f = acc_out + (int64_t)f * P;
+#pragma unroll
+    for (int t0 = 0; t0 < NT; t0 += G) {
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const int t = t0 + u;
+            if (t >= T0 && t < T1) {
+#pragma unroll
+                for (int rq = 0; rq < 4; ++rq)
+                    stage[((ROLE * G + u) * 4 + rq) * 64 + lane] =
+                        v4i{acc[t - T0][4 * rq], acc[t - T0][4 * rq + 1], acc[t - T0][4 * rq + 2],
+                            acc[t - T0][4 * rq + 3]};
+            }
+        }
+        __syncthreads();
+        const int NQ = (NT - t0 < G ? NT - t0 : G) * 256;   // (tile, rq, lane) quads this round
+#pragma unroll
+        for (int qq = tid; qq < NQ; qq += kMfmaThreads) {
+            const int u = qq >> 8, rq = (qq >> 6) & 3, ln = qq & 63;
+            const int t = t0 + u;
+            const int I = TRI ? tri_I_rt(t) : t / D;
+            const int J = TRI ? tri_J_rt(t) : t % D;
+            const int i0 = (row_blk + I) * 32 + 8 * rq + 4 * (ln >> 5);
+            const int j = (col_blk + J) * 32 + (ln & 31);
+            const int e = (u * 4 + rq) * 64 + ln;
+            const v4i rr = stage[(kRR * G * 4) * 64 + e];
+            const v4i ii = stage[(kII * G * 4) * 64 + e];
+            const v4i ir = stage[(kIR * G * 4) * 64 + e];
+            const v4i ri = stage[(kRI * G * 4) * 64 + e];
+            int64_t p = (int64_t)i0 * (i0 + 1) / 2 + j;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int i = i0 + m;
+                if (i < N && j <= i) {
+                    int re = (rr[m] >> 8) + (ii[m] >> 8);
+                    int im = (ir[m] >> 8) - (ri[m] >> 8);
+                    if (accumulate) {
+                        const int2 o = out_f[p];
+                        re += o.x;
+                        im += o.y;
+                    }
+                    out_f[p] = make_int2(re, im);
+                }
+                p += i + 1;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int D, bool TRI, int KC, int NBUF, int VEC>
+__device__ __forceinline__ void mfma4_dispatch(uint8_t *smem, const uint8_t *__restrict__ volts,
+                                               int64_t T, int F, int N, int f, int row_blk, int col_blk,
+                                               int2 *__restrict__ acc_out, int accumulate)
+{
+    // each wave runs one complete specialised body; all bodies execute the
+    // same sequence of work-group barriers
+    switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {
+#define XC_CASE(W)                                                                                  \
+    case W:                                                                                         \
+        mfma4_region<D, TRI, KC, NBUF, VEC, ((W) & 3), ((W) >> 2)>(smem, volts, T, F, N, f, row_blk,   \
+                                                                 col_blk, acc_out, accumulate);    \
+        break;
+        XC_CASE(0) XC_CASE(1) XC_CASE(2) XC_CASE(3) XC_CASE(4) XC_CASE(5) XC_CASE(6) XC_CASE(7)
+#undef XC_CASE
+    default: break;
+    }
+}
+
+}  // namespace
+}  // namespace xc

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 struct xcorr_ctx {
     xcorr_config cfg;
@@ -98,7 +99,7 @@ int validate(const xcorr_config *c, int64_t *t_max_out)
     if (c->path == XCORR_PATH_F16_MFMA && c->sample_bits != 8)
         return set_error(XCORR_E_INVAL, "the FP16 path takes 8+8-bit input only");
     if (c->tile != 0 && !xc::plan_supported(c->n_inputs, c->tile))
-        return set_error(XCORR_E_INVAL, "tile must be 0, 2, 3, 4, or 6 (6 only for N <= 192)");
+        return set_error(XCORR_E_INVAL, "tile must be 0, 2..4, 1 (N <= 32) or 5..6 (N <= 32*tile)");
     const int64_t tmax = c->sample_bits == 4 ? XCORR_TMAX_4BIT : XCORR_TMAX_8BIT;
     if (c->max_samples_per_dump < 0)
         return set_error(XCORR_E_INVAL, "max_samples_per_dump must be >= 0");
@@ -114,7 +115,61 @@ size_t acc_bytes(const xcorr_config &c)
     return (size_t)c.n_chans * (size_t)n_pairs(c.n_inputs) * 2 * 4;
 }
 
+// Region plan of a batch member: the context's own plan when its block size
+// is one the batched kernel carries (2, 3, 4), else the one of those with the
+// fewest tiles (padding included), the larger on a tie.
+xc::Plan batch_plan(const xcorr_ctx *c)
+{
+    if (c->plan.D >= 2 && c->plan.D <= 4)
+        return c->plan;
+    xc::Plan best;
+    int64_t best_tiles = -1;
+    for (int d = 2; d <= 4; ++d) {
+        const xc::Plan p = xc::make_plan(c->cfg.n_inputs, d);
+        const int64_t tiles = (int64_t)p.nseg * d * (d + 1) / 2 + (int64_t)p.nseg * (p.nseg - 1) / 2 * d * d;
+        if (best_tiles < 0 || tiles <= best_tiles) {
+            best = p;
+            best_tiles = tiles;
+        }
+    }
+    return best;
+}
+
+int device_cus(int *cus)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipGetDevice");
+    e = hipDeviceGetAttribute(cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipDeviceGetAttribute");
+    return XCORR_OK;
+}
+
+// Sequence-number bookkeeping shared by the single and batched ingest.
+void note_ingest(xcorr_ctx *ctx, int64_t n_samples, uint64_t seq)
+{
+    if (ctx->have_seq && seq != ctx->last_seq + 1) {
+        const uint64_t missing = seq > ctx->last_seq ? seq - ctx->last_seq - 1 : 1;
+        ctx->gaps += missing;
+        ctx->gaps_total += missing;
+    }
+    ctx->have_seq = true;
+    ctx->last_seq = seq;
+    ctx->acc_samples += n_samples;
+    ctx->total_samples += n_samples;
+    ++ctx->ingests;
+}
+
 }  // namespace
+
+struct xcorr_batch {
+    std::vector<xcorr_ctx *> ctx;
+    std::vector<xc::Plan> plan;
+    int *queue;
+    int grid;
+};
 
 extern "C" {
 
@@ -211,16 +266,7 @@ int xcorr_ingest(xcorr_ctx *ctx, const void *d_volts, int64_t n_samples, uint64_
             return hip_fail(e, "kernel launch");
         ++ctx->launches;
     }
-    if (ctx->have_seq && seq != ctx->last_seq + 1) {
-        const uint64_t missing = seq > ctx->last_seq ? seq - ctx->last_seq - 1 : 1;
-        ctx->gaps += missing;
-        ctx->gaps_total += missing;
-    }
-    ctx->have_seq = true;
-    ctx->last_seq = seq;
-    ctx->acc_samples += n_samples;
-    ctx->total_samples += n_samples;
-    ++ctx->ingests;
+    note_ingest(ctx, n_samples, seq);
     return XCORR_OK;
 }
 
@@ -265,6 +311,247 @@ int xcorr_destroy(xcorr_ctx *ctx)
     if (!ctx)
         return set_error(XCORR_E_INVAL, "ctx is NULL");
     delete ctx;
+    return XCORR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched persistent launch
+
+static int batch_check(xcorr_ctx *const *ctxs, int n)
+{
+    static_assert(XCORR_MAX_BATCH == xc::kMaxBatchArrays, "batch limit");
+    if (!ctxs || n < 1 || n > xc::kMaxBatchArrays)
+        return set_error(XCORR_E_INVAL, "a batch holds 1 to 16 contexts");
+    for (int a = 0; a < n; ++a) {
+        if (!ctxs[a])
+            return set_error(XCORR_E_INVAL, "NULL context in the batch");
+        if (ctxs[a]->cfg.sample_bits != 4 || ctxs[a]->cfg.path != XCORR_PATH_I8_MFMA)
+            return set_error(XCORR_E_INVAL, "the batched launch takes 4+4-bit int8-MFMA contexts");
+        for (int b = 0; b < a; ++b)
+            if (ctxs[b] == ctxs[a])
+                return set_error(XCORR_E_INVAL, "a context appears twice in the batch");
+    }
+    return XCORR_OK;
+}
+
+int xcorr_batch_query(xcorr_ctx *const *ctxs, int n, size_t *workspace_bytes)
+{
+    const int rc = batch_check(ctxs, n);
+    if (rc)
+        return rc;
+    if (workspace_bytes)
+        *workspace_bytes = 256;
+    return XCORR_OK;
+}
+
+int xcorr_batch_init(xcorr_ctx *const *ctxs, int n, void *d_workspace, size_t ws_bytes, xcorr_batch **out)
+{
+    int rc = batch_check(ctxs, n);
+    if (rc)
+        return rc;
+    if (!out)
+        return set_error(XCORR_E_INVAL, "out is NULL");
+    if (!d_workspace || ws_bytes < 256)
+        return set_error(XCORR_E_NOMEM, "batch workspace missing or smaller than 256 bytes");
+    if ((uintptr_t)d_workspace % 256)
+        return set_error(XCORR_E_INVAL, "workspace must be 256-byte aligned");
+    int cus = 0;
+    rc = device_cus(&cus);
+    if (rc)
+        return rc;
+    xcorr_batch *b = new (std::nothrow) xcorr_batch();
+    if (!b)
+        return set_error(XCORR_E_NOMEM, "host allocation failed");
+    for (int a = 0; a < n; ++a) {
+        b->ctx.push_back(ctxs[a]);
+        b->plan.push_back(batch_plan(ctxs[a]));
+    }
+    b->queue = static_cast<int *>(d_workspace);
+    b->grid = cus;   // one 512-thread work-group per CU (LDS-limited), persistent
+    hipError_t e = xc::launch_fill_zero(b->queue, xc::kBatchQueueInts, nullptr);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) {
+        delete b;
+        return hip_fail(e, "batch queue initialisation");
+    }
+    *out = b;
+    return XCORR_OK;
+}
+
+int xcorr_batch_ingest(xcorr_batch *b, const void *const *d_volts, const int64_t *n_samples,
+                       const uint64_t *seqs, void *stream)
+{
+    if (!b || !d_volts || !n_samples)
+        return set_error(XCORR_E_INVAL, "batch, d_volts or n_samples is NULL");
+    const int n = (int)b->ctx.size();
+    int64_t longest = 0;
+    for (int a = 0; a < n; ++a) {
+        const xcorr_ctx *c = b->ctx[a];
+        if (n_samples[a] < 0)
+            return set_error(XCORR_E_INVAL, "n_samples must be >= 0");
+        if (n_samples[a] > 0 && !d_volts[a])
+            return set_error(XCORR_E_INVAL, "d_volts is NULL for an array with samples");
+        if (n_samples[a] > c->max_dump - c->acc_samples)
+            return set_error(XCORR_E_OVERFLOW, "integration would exceed max_samples_per_dump");
+        longest = std::max(longest, n_samples[a]);
+    }
+    if (longest == 0)
+        return set_error(XCORR_E_INVAL, "no array has samples to ingest");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int64_t L = xc::kMaxSamplesPerLaunch4;
+    for (int64_t t0 = 0; t0 < longest; t0 += L) {
+        xc::BatchArgs args{};
+        int vec = 1;
+        int64_t items = 0;
+        for (int a = 0; a < n; ++a) {
+            if (n_samples[a] <= t0)
+                continue;
+            const xcorr_ctx *c = b->ctx[a];
+            const xc::Plan &pl = b->plan[a];
+            const int F = c->cfg.n_chans, N = c->cfg.n_inputs;
+            xc::BatchArray &A = args.a[args.n++];
+            A.volts = static_cast<const uint8_t *>(d_volts[a]) + t0 * (int64_t)F * N;
+            A.acc = static_cast<int2 *>(c->ws);
+            A.T = std::min(L, n_samples[a] - t0);
+            A.F = F;
+            A.N = N;
+            A.D = pl.D;
+            A.nseg = pl.nseg;
+            A.regions = pl.regions;
+            A.accumulate = (c->acc_samples > 0 || t0 > 0) ? 1 : 0;
+            A.item_begin = (int)items;
+            items += (int64_t)F * pl.regions;
+            if (N % 16 || (uintptr_t)A.volts % 16 || 64LL * F * N >= (1LL << 31) - 16)
+                vec = 0;
+        }
+        if (items > (1LL << 30))
+            return set_error(XCORR_E_INVAL, "too many work items in one batch");
+        args.total = (int)items;
+        const hipError_t e = xc::launch_batch4(args, b->queue, vec, std::min<int64_t>(b->grid, items), s);
+        if (e != hipSuccess)
+            return hip_fail(e, "batch launch");
+        for (int a = 0; a < n; ++a)
+            if (n_samples[a] > t0)
+                ++b->ctx[a]->launches;
+    }
+    for (int a = 0; a < n; ++a)
+        if (n_samples[a] > 0) {
+            xcorr_ctx *c = b->ctx[a];
+            note_ingest(c, n_samples[a], seqs ? seqs[a] : (c->have_seq ? c->last_seq + 1 : 0));
+        }
+    return XCORR_OK;
+}
+
+int xcorr_batch_tiles(const xcorr_batch *b, int32_t *tiles)
+{
+    if (!b || !tiles)
+        return set_error(XCORR_E_INVAL, "batch or tiles is NULL");
+    for (size_t a = 0; a < b->plan.size(); ++a)
+        tiles[a] = b->plan[a].D;
+    return XCORR_OK;
+}
+
+int xcorr_batch_destroy(xcorr_batch *b)
+{
+    if (!b)
+        return set_error(XCORR_E_INVAL, "batch is NULL");
+    delete b;
+    return XCORR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner
+
+static int64_t tune_samples() { return 2048; }
+
+int xcorr_autotune_query(const xcorr_config *cfg, size_t *scratch_bytes)
+{
+    const int rc = validate(cfg, nullptr);
+    if (rc)
+        return rc;
+    if (cfg->path == XCORR_PATH_PLAIN)
+        return set_error(XCORR_E_INVAL, "the plain path has no tile to tune");
+    const size_t volts = (size_t)tune_samples() * cfg->n_chans * cfg->n_inputs * (cfg->sample_bits == 4 ? 1 : 2);
+    if (scratch_bytes)
+        *scratch_bytes = round_up(acc_bytes(*cfg), 256) + round_up(volts, 256);
+    return XCORR_OK;
+}
+
+int xcorr_autotune(const xcorr_config *cfg, void *d_scratch, size_t scratch_bytes, void *stream,
+                   int32_t *best_tile)
+{
+    size_t need = 0;
+    int rc = xcorr_autotune_query(cfg, &need);
+    if (rc)
+        return rc;
+    if (!best_tile)
+        return set_error(XCORR_E_INVAL, "best_tile is NULL");
+    if (!d_scratch || scratch_bytes < need)
+        return set_error(XCORR_E_NOMEM, "scratch missing or smaller than xcorr_autotune_query's size");
+    if ((uintptr_t)d_scratch % 256)
+        return set_error(XCORR_E_INVAL, "scratch must be 256-byte aligned");
+    const xcorr_config &c = *cfg;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    uint8_t *base = static_cast<uint8_t *>(d_scratch);
+    void *acc = base;
+    uint8_t *volts = base + round_up(acc_bytes(c), 256);
+    const int64_t T = tune_samples();
+    const int64_t vbytes = T * c.n_chans * c.n_inputs * (c.sample_bits == 4 ? 1 : 2);
+    hipError_t e = xc::launch_fill_pattern(volts, vbytes, c.sample_bits == 8, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "autotune input fill");
+    hipEvent_t ev[2];
+    if ((e = hipEventCreate(&ev[0])) != hipSuccess)
+        return hip_fail(e, "hipEventCreate");
+    if ((e = hipEventCreate(&ev[1])) != hipSuccess) {
+        hipEventDestroy(ev[0]);
+        return hip_fail(e, "hipEventCreate");
+    }
+    int best = 0;
+    float best_ms = 0.f;
+    for (int d = 1; d <= 6 && e == hipSuccess; ++d) {
+        if (!xc::plan_supported(c.n_inputs, d))
+            continue;
+        const xc::Plan pl = xc::make_plan(c.n_inputs, d);
+        auto run = [&](int accumulate) {
+            return c.sample_bits == 4
+                       ? xc::launch_mfma4(pl, 64, volts, T, c.n_chans, c.n_inputs, static_cast<int2 *>(acc),
+                                          accumulate, s)
+                       : xc::launch_mfma8(pl, c.path == XCORR_PATH_F16_MFMA, volts, T, c.n_chans, c.n_inputs,
+                                          acc, accumulate, s);
+        };
+        constexpr int kReps = 5;
+        e = run(0);   // warm-up
+        if (e == hipSuccess)
+            e = hipEventRecord(ev[0], s);
+        for (int r = 0; r < kReps && e == hipSuccess; ++r)
+            e = run(1);
+        if (e == hipSuccess)
+            e = hipEventRecord(ev[1], s);
+        if (e == hipSuccess)
+            e = hipEventSynchronize(ev[1]);
+        float ms = 0.f;
+        if (e == hipSuccess)
+            e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+        if (e == hipSuccess && (best == 0 || ms < best_ms)) {
+            best = d;
+            best_ms = ms;
+        }
+    }
+    hipEventDestroy(ev[0]);
+    hipEventDestroy(ev[1]);
+    if (e != hipSuccess)
+        return hip_fail(e, "autotune timing");
+    *best_tile = best;
+    const char *path = std::getenv("XCORR_TUNE_CACHE");
+    if (path && *path) {
+        FILE *fh = std::fopen(path, "a");
+        if (!fh)
+            return set_error(XCORR_E_INVAL, std::string("cannot append to the tune cache ") + path);
+        std::fprintf(fh, "%d %d %d %d %d\n", c.sample_bits, c.n_inputs, c.n_chans, c.path, best);
+        std::fclose(fh);
+    }
     return XCORR_OK;
 }
 

@@ -50,4 +50,34 @@ hipError_t launch_mfma8_d6(const Plan &pl, bool f16, const uint8_t *volts, int64
 
 hipError_t launch_dump(const void *acc, void *out, int64_t bytes, int empty, hipStream_t s);
 
+// Batched persistent launch (4+4-bit, int8 MFMA): one kernel drains a work
+// queue of (array, channel, region) items for up to kMaxBatchArrays arrays of
+// uneven N, F and sample counts.  The descriptors travel by value in the
+// kernel arguments, so a captured graph holds everything it needs.
+constexpr int kMaxBatchArrays = 16;
+constexpr int kBatchQueueInts = 16;   // 8 per-XCD queue heads, a done counter, padding
+
+struct BatchArray {
+    const uint8_t *volts;   // [T][F][N] packed 4+4-bit
+    int2 *acc;              // [F][P] accumulators
+    int64_t T;              // samples in this launch (>= 1)
+    int F, N;
+    int D, nseg, regions;   // region plan, D in {2, 3, 4}
+    int accumulate;
+    int item_begin;         // first work item of this array
+};
+
+struct BatchArgs {
+    int n;                  // arrays
+    int total;              // work items
+    BatchArray a[kMaxBatchArrays];
+};
+
+// queue: kBatchQueueInts ints of device memory, zero before the first launch;
+// every launch leaves it zero again.  vec: every array has N % 16 == 0, a
+// 16-byte aligned input and 64 * F * N < 2^31 - 16.
+hipError_t launch_batch4(const BatchArgs &args, int *queue, int vec, int grid, hipStream_t s);
+hipError_t launch_fill_zero(int *p, int n, hipStream_t s);
+hipError_t launch_fill_pattern(uint8_t *p, int64_t n, int eight_bit, hipStream_t s);
+
 }  // namespace xc

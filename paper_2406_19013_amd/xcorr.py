@@ -28,6 +28,7 @@ LAYOUT_TFN = 0
 
 TMAX_4BIT = 16_777_215
 TMAX_8BIT = 66_572
+MAX_BATCH = 16
 
 
 class XcorrError(RuntimeError):
@@ -92,6 +93,13 @@ def load(path: str | None = None):
             "xcorr_dump": [vp, vp, ctypes.POINTER(i64), ctypes.POINTER(u64), vp],
             "xcorr_stats": [vp, ctypes.POINTER(Stats)],
             "xcorr_destroy": [vp],
+            "xcorr_batch_query": [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(sz)],
+            "xcorr_batch_init": [ctypes.POINTER(vp), ctypes.c_int, vp, sz, ctypes.POINTER(vp)],
+            "xcorr_batch_ingest": [vp, ctypes.POINTER(vp), ctypes.POINTER(i64), ctypes.POINTER(u64), vp],
+            "xcorr_batch_tiles": [vp, ctypes.POINTER(ctypes.c_int32)],
+            "xcorr_batch_destroy": [vp],
+            "xcorr_autotune_query": [cfgp, ctypes.POINTER(sz)],
+            "xcorr_autotune": [cfgp, vp, sz, vp, ctypes.POINTER(ctypes.c_int32)],
         }
         for name, args in sig.items():
             fn = getattr(lib, name)
@@ -172,6 +180,69 @@ def xcorr_destroy(ctx):
     _check(load().xcorr_destroy(ctx), "xcorr_destroy")
 
 
+def _ctx_array(ctxs):
+    arr = (ctypes.c_void_p * len(ctxs))()
+    for k, c in enumerate(ctxs):
+        arr[k] = c.value if isinstance(c, ctypes.c_void_p) else c
+    return arr
+
+
+def xcorr_batch_query(ctxs) -> int:
+    ws = ctypes.c_size_t()
+    _check(load().xcorr_batch_query(_ctx_array(ctxs), len(ctxs), ctypes.byref(ws)), "xcorr_batch_query")
+    return ws.value
+
+
+def xcorr_batch_init(ctxs, workspace, ws_bytes: int | None = None) -> ctypes.c_void_p:
+    b = ctypes.c_void_p()
+    nbytes = ws_bytes if ws_bytes is not None else workspace.numel() * workspace.element_size()
+    _check(load().xcorr_batch_init(_ctx_array(ctxs), len(ctxs), ctypes.c_void_p(workspace.data_ptr()),
+                                   nbytes, ctypes.byref(b)), "xcorr_batch_init")
+    return b
+
+
+def xcorr_batch_ingest(batch, volts, n_samples, seqs=None, stream=None):
+    """volts: one device tensor (or None for an array left out) per array."""
+    n = len(n_samples)
+    vp = (ctypes.c_void_p * n)(*[(v.data_ptr() if v is not None else None) for v in volts])
+    ns = (ctypes.c_int64 * n)(*[int(x) for x in n_samples])
+    sq = (ctypes.c_uint64 * n)(*[int(x) for x in seqs]) if seqs is not None else None
+    _check(load().xcorr_batch_ingest(batch, vp, ns, sq, _stream_handle(stream)), "xcorr_batch_ingest")
+
+
+def xcorr_batch_tiles(batch, n: int) -> list:
+    t = (ctypes.c_int32 * n)()
+    _check(load().xcorr_batch_tiles(batch, t), "xcorr_batch_tiles")
+    return list(t)
+
+
+def xcorr_batch_destroy(batch):
+    _check(load().xcorr_batch_destroy(batch), "xcorr_batch_destroy")
+
+
+def xcorr_autotune_query(cfg: Config) -> int:
+    sz = ctypes.c_size_t()
+    _check(load().xcorr_autotune_query(ctypes.byref(cfg), ctypes.byref(sz)), "xcorr_autotune_query")
+    return sz.value
+
+
+def xcorr_autotune(cfg: Config, scratch, stream=None) -> int:
+    best = ctypes.c_int32()
+    _check(load().xcorr_autotune(ctypes.byref(cfg), ctypes.c_void_p(scratch.data_ptr()),
+                                 scratch.numel() * scratch.element_size(), _stream_handle(stream),
+                                 ctypes.byref(best)), "xcorr_autotune")
+    return best.value
+
+
+def autotune(n_inputs: int, n_chans: int, sample_bits: int = 4, path: int = PATH_I8_MFMA, device="cuda",
+             stream=None) -> int:
+    """Run the autotuner with a torch-allocated scratch; returns the best tile."""
+    import torch
+    cfg = make_config(n_inputs, n_chans, sample_bits, path)
+    scratch = torch.empty(xcorr_autotune_query(cfg), dtype=torch.uint8, device=device)
+    return xcorr_autotune(cfg, scratch, stream)
+
+
 def xcorr_strerror(code: int) -> str:
     return load().xcorr_strerror(code).decode()
 
@@ -221,6 +292,43 @@ class Correlator:
         if self.ctx:
             xcorr_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """A batched persistent launch over several Correlators (4+4-bit int8 MFMA).
+
+    ``ingest([volts_0, volts_1, ...])`` correlates every array in one kernel;
+    dumps stay per Correlator.  The Correlators must outlive the Batch.
+    """
+
+    def __init__(self, correlators, device="cuda"):
+        import torch
+        self.members = list(correlators)
+        ctxs = [c.ctx for c in self.members]
+        self.ws_bytes = xcorr_batch_query(ctxs)
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        self.batch = xcorr_batch_init(ctxs, self.workspace, self.ws_bytes)
+        self.tiles = xcorr_batch_tiles(self.batch, len(ctxs))
+
+    def ingest(self, volts, n_samples=None, seqs=None, stream=None):
+        ns = [0 if v is None else v.shape[0] for v in volts] if n_samples is None else list(n_samples)
+        if seqs is None:
+            seqs = [c._seq for c in self.members]
+        xcorr_batch_ingest(self.batch, volts, ns, seqs, stream)
+        for c, n, s in zip(self.members, ns, seqs):
+            if n > 0:
+                c._seq = s + 1
+
+    def close(self):
+        if self.batch:
+            xcorr_batch_destroy(self.batch)
+            self.batch = None
 
     def __del__(self):
         try:

@@ -86,6 +86,42 @@ def test_null_context_is_rejected(lib):
     assert lib.xcorr_stats(None, None) == X.XCORR_E_INVAL
 
 
+def test_batch_calls_reject_bad_arguments_on_the_host(lib):
+    ws = ctypes.c_size_t()
+    assert lib.xcorr_batch_query(None, 1, ctypes.byref(ws)) == X.XCORR_E_INVAL
+    nulls = (ctypes.c_void_p * 17)()
+    for n in (0, 17):
+        assert lib.xcorr_batch_query(nulls, n, ctypes.byref(ws)) == X.XCORR_E_INVAL
+    assert lib.xcorr_batch_query(nulls, 2, ctypes.byref(ws)) == X.XCORR_E_INVAL   # NULL members
+    b = ctypes.c_void_p()
+    assert lib.xcorr_batch_init(nulls, 1, ctypes.c_void_p(256), 256, ctypes.byref(b)) == X.XCORR_E_INVAL
+    assert lib.xcorr_batch_ingest(None, None, None, None, None) == X.XCORR_E_INVAL
+    assert lib.xcorr_batch_destroy(None) == X.XCORR_E_INVAL
+    assert lib.xcorr_batch_tiles(None, None) == X.XCORR_E_INVAL
+    assert not b.value
+
+
+def test_autotune_query_sizes_and_rejections():
+    cfg = X.make_config(192, 1024, 4, X.PATH_I8_MFMA)
+    ws, _, _ = X.xcorr_query(cfg)
+    assert X.xcorr_autotune_query(cfg) == ws + 2048 * 1024 * 192
+    cfg8 = X.make_config(96, 16, 8, X.PATH_F16_MFMA)
+    ws8, _, _ = X.xcorr_query(cfg8)
+    assert X.xcorr_autotune_query(cfg8) == ws8 + 2048 * 16 * 96 * 2
+    with pytest.raises(X.XcorrError) as ei:
+        X.xcorr_autotune_query(X.make_config(16, 8, 4, X.PATH_PLAIN))
+    assert ei.value.code == X.XCORR_E_INVAL
+
+
+def test_autotune_rejects_short_scratch_before_any_device_call(lib):
+    cfg = X.make_config(64, 8, 4, X.PATH_I8_MFMA)
+    best = ctypes.c_int32(-7)
+    assert lib.xcorr_autotune(ctypes.byref(cfg), None, 1 << 30, None, ctypes.byref(best)) == X.XCORR_E_NOMEM
+    assert lib.xcorr_autotune(ctypes.byref(cfg), ctypes.c_void_p(256), 16, None, ctypes.byref(best)) == X.XCORR_E_NOMEM
+    assert lib.xcorr_autotune(ctypes.byref(cfg), ctypes.c_void_p(256), 1 << 30, None, None) == X.XCORR_E_INVAL
+    assert best.value == -7
+
+
 def test_strerror_covers_codes():
     for c in (0, -1, -2, -3, -4, -5):
         assert X.xcorr_strerror(c) and X.xcorr_strerror(c) != "unknown error"

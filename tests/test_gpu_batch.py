@@ -1,0 +1,204 @@
+"""GPU parity of the batched persistent launch (several arrays of uneven N, F
+and sample count in one kernel), its HIP-graph replay, and the autotuner.
+Integer results must match the oracle bit for bit."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2406_19013_amd import synth
+from paper_2406_19013_amd import xcorr as X
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def want(v_cpu, N, F):
+    return oracle.to_int32(oracle.xcorr(v_cpu.numpy(), 4, v_cpu.shape[0], F, N))
+
+
+def dump_all(cors):
+    outs = []
+    for c in cors:
+        o, n, _ = c.dump()
+        outs.append((o, n))
+    torch.cuda.synchronize()
+    return [(o.cpu().numpy(), n) for o, n in outs]
+
+
+# (N, F, T): uneven inputs, channels and sample counts; all N % 16 == 0 takes
+# the LDS-DMA kernel, any other N the register-staged one
+VEC_SET = [(64, 6, 300), (192, 3, 1000), (256, 2, 77), (32, 5, 2048), (512, 1, 130)]
+RAGGED_SET = [(100, 3, 77), (20, 4, 515), (192, 2, 64), (33, 3, 200)]
+
+
+@pytest.mark.parametrize("arrays", [VEC_SET, RAGGED_SET], ids=["vec", "ragged"])
+def test_batch_matches_oracle(arrays):
+    _say(f"batch arrays {arrays}")
+    vs = [synth.uniform_volts4(N, F, T, seed=(3001, N, F, T)) for N, F, T in arrays]
+    cors = [X.Correlator(N, F, 4, X.PATH_I8_MFMA) for N, F, _ in arrays]
+    b = X.Batch(cors)
+    assert all(t in (2, 3, 4) for t in b.tiles)
+    b.ingest([v.cuda() for v in vs])
+    for (got, n), v, (N, F, T) in zip(dump_all(cors), vs, arrays):
+        assert n == T
+        assert np.array_equal(got, want(v, N, F)), (N, F, T)
+    b.close()
+
+
+def test_batch_uneven_ingests_accumulate_and_skip():
+    """Three batched ingests with per-array counts (some 0) add up to the
+    oracle over each array's concatenated samples."""
+    arrays = [(64, 3), (96, 2), (20, 4)]
+    counts = [[100, 0, 33], [1, 50, 0], [129, 7, 64]]
+    cors = [X.Correlator(N, F, 4, X.PATH_I8_MFMA) for N, F in arrays]
+    b = X.Batch(cors)
+    parts = [[] for _ in arrays]
+    for k, ns in enumerate(counts):
+        vols = []
+        for a, ((N, F), n) in enumerate(zip(arrays, ns)):
+            if n == 0:
+                vols.append(None)
+                continue
+            v = synth.uniform_volts4(N, F, n, seed=(3002, a, k))
+            parts[a].append(v)
+            vols.append(v.cuda())
+        b.ingest(vols, ns)
+    for (got, n), (N, F), p in zip(dump_all(cors), arrays, parts):
+        v = torch.cat(p)
+        assert n == v.shape[0]
+        assert np.array_equal(got, want(v, N, F))
+    b.close()
+
+
+def test_batch_long_ingest_splits_launches():
+    """140,001 samples of -8-8i on one array, 1000 on another: the host splits
+    the long one across two launches (131,071 samples per launch)."""
+    T1 = 140_001
+    v1 = torch.full((T1, 1, 16), 0x88, dtype=torch.uint8)
+    v2 = synth.uniform_volts4(48, 2, 1000, seed=(3003,))
+    cors = [X.Correlator(16, 1, 4, X.PATH_I8_MFMA), X.Correlator(48, 2, 4, X.PATH_I8_MFMA)]
+    b = X.Batch(cors)
+    b.ingest([v1.cuda(), v2.cuda()])
+    assert cors[0].stats()["kernel_launches"] == 2 and cors[1].stats()["kernel_launches"] == 1
+    (g1, n1), (g2, n2) = dump_all(cors)
+    assert n1 == T1 and np.all(g1[..., 0] == 128 * T1) and np.all(g1[..., 1] == 0)
+    assert np.array_equal(g2, want(v2, 48, 2))
+    b.close()
+
+
+def test_batch_repeated_launches_reset_queue():
+    """Five launches in a row: the work queue is back at zero after each, so
+    every launch covers every item (the sum is 5x one ingest)."""
+    arrays = [(64, 4, 256), (160, 2, 128)]
+    vs = [synth.uniform_volts4(N, F, T, seed=(3004, N)) for N, F, T in arrays]
+    cors = [X.Correlator(N, F, 4, X.PATH_I8_MFMA) for N, F, _ in arrays]
+    b = X.Batch(cors)
+    vd = [v.cuda() for v in vs]
+    for _ in range(5):
+        b.ingest(vd)
+    for (got, n), v, (N, F, T) in zip(dump_all(cors), vs, arrays):
+        assert n == 5 * T
+        assert np.array_equal(got, 5 * want(v, N, F).astype(np.int64))
+    b.close()
+
+
+def test_batched_workload_matches_single_path():
+    """The four-array workload (64x256, 192x1024, 256x512, 512x128 inputs x
+    channels, 2048 samples): batch equals the single-array path over every
+    output, and the oracle on sampled channels."""
+    _say("batched workload full size")
+    vs = synth.batched(device="cuda")
+    cors = [X.Correlator(N, F, 4, X.PATH_I8_MFMA) for N, F in synth.BATCH_ARRAYS]
+    b = X.Batch(cors)
+    b.ingest(vs)
+    outs = [c.dump()[0] for c in cors]
+    for v, (N, F), got in zip(vs, synth.BATCH_ARRAYS, outs):
+        s = X.Correlator(N, F, 4, X.PATH_I8_MFMA)
+        s.ingest(v)
+        ref, _, _ = s.dump()
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref), (N, F)
+        chans = [0, F // 2, F - 1]
+        vc = np.ascontiguousarray(v[:, chans].cpu().numpy())
+        assert np.array_equal(got[chans].cpu().numpy(),
+                              oracle.to_int32(oracle.xcorr(vc, 4, v.shape[0], len(chans), N)))
+        s.close()
+    b.close()
+
+
+def test_batch_graph_replay():
+    """Capture [batched ingest, per-array dumps] in a HIP graph; between
+    replays refill the inputs and run eager work on the same arrays; every
+    replay must equal the oracle for the inputs it saw."""
+    arrays = [(64, 4, 512), (192, 2, 256), (100, 3, 96)]
+    cors = [X.Correlator(N, F, 4, X.PATH_I8_MFMA) for N, F, _ in arrays]
+    b = X.Batch(cors)
+    vin = [torch.empty((T, F, N), dtype=torch.uint8, device="cuda") for N, F, T in arrays]
+    outs = [torch.empty((F, N * (N + 1) // 2, 2), dtype=torch.int32, device="cuda") for N, F, _ in arrays]
+    sets = [[synth.uniform_volts4(N, F, T, seed=(3005, k, N)) for N, F, T in arrays] for k in range(3)]
+    for d, v in zip(vin, sets[0]):
+        d.copy_(v)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.graph(g, stream=side):
+        b.ingest(vin)
+        for c, o in zip(cors, outs):
+            c.dump(o)
+    torch.cuda.synchronize()
+    for k in range(3):
+        for d, v in zip(vin, sets[k]):
+            d.copy_(v)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for o, v, (N, F, T) in zip(outs, sets[k], arrays):
+            assert np.array_equal(o.cpu().numpy(), want(v, N, F)), (k, N)
+        # eager work in between: a batched ingest and dumps of other data
+        b.ingest([x.cuda() for x in sets[(k + 1) % 3]])
+        eager = dump_all(cors)
+        for (e, n), v, (N, F, T) in zip(eager, sets[(k + 1) % 3], arrays):
+            assert n == T and np.array_equal(e, want(v, N, F))
+    b.close()
+
+
+def test_batch_rejects_mixed_paths():
+    c4 = X.Correlator(64, 2, 4, X.PATH_I8_MFMA)
+    c8 = X.Correlator(64, 2, 8, X.PATH_I8_MFMA)
+    with pytest.raises(X.XcorrError) as ei:
+        X.Batch([c4, c8])
+    assert ei.value.code == X.XCORR_E_INVAL
+    b = X.Batch([c4])
+    with pytest.raises(X.XcorrError) as ei:
+        # refused on the host before anything is enqueued: the buffer is never read
+        b.ingest([torch.zeros((1, 2, 64), dtype=torch.uint8, device="cuda")], [X.TMAX_4BIT + 1])
+    assert ei.value.code == X.XCORR_E_OVERFLOW
+    b.close()
+
+
+@pytest.mark.parametrize("bits,path,N,F", [(4, X.PATH_I8_MFMA, 192, 64), (8, X.PATH_I8_MFMA, 96, 32),
+                                           (8, X.PATH_F16_MFMA, 64, 16)])
+def test_autotune_picks_supported_tile_and_caches(tmp_path, monkeypatch, bits, path, N, F):
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("XCORR_TUNE_CACHE", str(cache))
+    best = X.autotune(N, F, bits, path)
+    assert 1 <= best <= 6
+    lines = cache.read_text().split("\n")
+    assert lines[0].split() == [str(bits), str(N), str(F), str(path), str(best)]
+    c = X.Correlator(N, F, bits, path)
+    assert c.stats()["tile"] == best
+    v = (synth.uniform_volts4(N, F, 70, seed=(3006,)) if bits == 4
+         else synth.uniform_volts8(N, F, 70, seed=(3006,)))
+    c.ingest(v.cuda())
+    got, _, _ = c.dump()
+    exp = oracle.xcorr(v.numpy(), bits, 70, F, N)
+    if path == X.PATH_F16_MFMA:
+        assert np.array_equal(got.cpu().numpy().astype(np.int64), exp)
+    else:
+        assert np.array_equal(got.cpu().numpy(), oracle.to_int32(exp))
+    c.close()
