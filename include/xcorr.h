@@ -67,6 +67,7 @@ extern "C" {
 
 typedef struct xcorr_ctx xcorr_ctx;
 typedef struct xcorr_batch xcorr_batch;
+typedef struct xcorr_pipe xcorr_pipe;
 
 typedef struct {
     int32_t n_inputs;     /* N >= 1 (input k = 2*feed + polarisation) */
@@ -189,6 +190,51 @@ int xcorr_batch_destroy(xcorr_batch *b);
 int xcorr_autotune_query(const xcorr_config *cfg, size_t *scratch_bytes);
 int xcorr_autotune(const xcorr_config *cfg, void *d_scratch, size_t scratch_bytes, void *stream,
                    int32_t *best_tile);
+/*
+ * Streaming loop (the X-engine node's packet ring feeding the correlator,
+ * which integrates and hands each integration to an output stage: Section
+ * 2.3).  A pipe wraps one context: each xcorr_pipe_push submits one block of
+ * block_samples samples; a host block (on_host = 1, pinned host memory) is
+ * copied on `copy_stream` into the next of n_slots device ring slots (the slot
+ * is reused once its previous ingest has finished), then ingested on
+ * `compute_stream` after the copy; a device block (on_host = 0) is ingested
+ * in place.  Every dump_every-th block the integration is dumped into d_out
+ * (required on that push, *dumped = 1).  Each block's latency, from the start
+ * of its transfer (host blocks) or of its ingest (device blocks) to the end
+ * of its ingest (and dump), is taken from HIP events; xcorr_pipe_stats
+ * reports nearest-rank p50 / p99 and the maximum over the reaped blocks
+ * (xcorr_pipe_drain waits for every block in flight).  Calls are
+ * asynchronous except that at most max(8, 4 n_slots) blocks are in flight:
+ * a push beyond that waits for the oldest.  The host block, d_out and device
+ * blocks must stay valid until the streams pass them.
+ *
+ * xcorr_pipe_query : ring bytes (n_slots slots of 256-byte-rounded blocks).
+ * xcorr_pipe_init  : ctx borrowed; d_ring may be NULL for device blocks only.
+ *   Errors: XCORR_E_INVAL, XCORR_E_NOMEM (short or misaligned ring),
+ *   XCORR_E_OVERFLOW (dump_every * block_samples > max_samples_per_dump).
+ *
+ * Admission by memory: xcorr_admit walks cfgs[0..n) in order and admits an
+ * array (admitted[a] = 1) while the running device footprint (workspace +
+ * dump buffer + n_slots[a] ring slots of block_samples[a] samples; NULL
+ * arrays count 0) stays within budget_bytes; *used_bytes = the admitted
+ * total.  Pure host.
+ */
+typedef struct {
+    int64_t blocks, dumps, latencies;
+    double p50_ms, p99_ms, max_ms, mean_ms;
+} xcorr_pipe_stats_t;
+
+int xcorr_pipe_query(const xcorr_ctx *ctx, int n_slots, int64_t block_samples, size_t *ring_bytes);
+int xcorr_pipe_init(xcorr_ctx *ctx, int n_slots, int64_t block_samples, int64_t dump_every, void *d_ring,
+                    size_t ring_bytes, void *copy_stream, void *compute_stream, xcorr_pipe **out);
+int xcorr_pipe_push(xcorr_pipe *p, const void *block, int on_host, uint64_t seq, void *d_out, int *dumped);
+int xcorr_pipe_drain(xcorr_pipe *p);
+int xcorr_pipe_stats(const xcorr_pipe *p, xcorr_pipe_stats_t *out);
+int xcorr_pipe_reset_latency(xcorr_pipe *p);
+int xcorr_pipe_destroy(xcorr_pipe *p);
+int xcorr_admit(const xcorr_config *cfgs, int n, const int64_t *block_samples, const int32_t *n_slots,
+                size_t budget_bytes, int32_t *admitted, size_t *used_bytes);
+
 const char *xcorr_strerror(int code);
 /* Detail of the last XCORR_E_HIP / XCORR_E_DEVICE on this thread. */
 const char *xcorr_last_error(void);

@@ -43,6 +43,17 @@ int set_error(int code, const std::string &msg)
     return code;
 }
 
+}  // namespace
+
+int xc::api_error(int code, const std::string &msg) { return set_error(code, msg); }
+
+xc::CtxShape xc::ctx_shape(const xcorr_ctx *c)
+{
+    return {c->cfg.n_inputs, c->cfg.n_chans, c->cfg.sample_bits, c->cfg.path, c->max_dump};
+}
+
+namespace {
+
 int hip_fail(hipError_t e, const char *what)
 {
     return set_error(XCORR_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
@@ -505,7 +516,7 @@ int xcorr_autotune(const xcorr_config *cfg, void *d_scratch, size_t scratch_byte
     if ((e = hipEventCreate(&ev[0])) != hipSuccess)
         return hip_fail(e, "hipEventCreate");
     if ((e = hipEventCreate(&ev[1])) != hipSuccess) {
-        hipEventDestroy(ev[0]);
+        (void)hipEventDestroy(ev[0]);
         return hip_fail(e, "hipEventCreate");
     }
     int best = 0;
@@ -539,8 +550,8 @@ int xcorr_autotune(const xcorr_config *cfg, void *d_scratch, size_t scratch_byte
             best_ms = ms;
         }
     }
-    hipEventDestroy(ev[0]);
-    hipEventDestroy(ev[1]);
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
     if (e != hipSuccess)
         return hip_fail(e, "autotune timing");
     *best_tile = best;

@@ -2,6 +2,9 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <string>
+
+struct xcorr_ctx;
 
 namespace xc {
 
@@ -16,6 +19,14 @@ struct Plan {
     int nseg = 0;           // diagonal segments
     int regions = 0;        // regions per channel
 };
+
+// Host-side helpers of the C ABI shared between its source files.
+int api_error(int code, const std::string &msg);   // records the detail, returns code
+struct CtxShape {
+    int n_inputs, n_chans, sample_bits, path;
+    int64_t max_samples_per_dump;
+};
+CtxShape ctx_shape(const xcorr_ctx *ctx);
 
 Plan make_plan(int N, int D);
 bool plan_supported(int N, int D);

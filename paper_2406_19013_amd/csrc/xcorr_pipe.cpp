@@ -1,0 +1,350 @@
+// Streaming runtime of the C ABI: a ring of device block slots between a
+// copy stream (host -> device transfers) and a compute stream (ingest, and a
+// dump every `dump_every` blocks), with per-block latency taken from HIP
+// events; plus admission of arrays against a device-memory budget.
+//
+// The paper's X-engine node runs a ring buffer of received packets feeding
+// the correlator, which integrates and hands each integration to an output
+// stage (Section 2.3); this file is that loop around one context.  The
+// library allocates no device memory: the ring is the caller's.
+#include "xcorr.h"
+#include "xcorr_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <deque>
+#include <new>
+#include <string>
+#include <vector>
+
+namespace {
+
+using xc::api_error;
+
+int hip_err(hipError_t e, const char *what)
+{
+    return api_error(XCORR_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+struct Record {
+    hipEvent_t begin, end;
+};
+
+}  // namespace
+
+struct xcorr_pipe {
+    xcorr_ctx *ctx = nullptr;
+    int n_slots = 0;
+    int64_t block_samples = 0;
+    int64_t dump_every = 0;
+    size_t block_bytes = 0;
+    uint8_t *ring = nullptr;
+    hipStream_t copy = nullptr, compute = nullptr;
+    std::vector<hipEvent_t> copied, consumed;   // per slot
+    std::vector<bool> slot_used;
+    std::deque<Record> pending;                 // latency records in flight
+    std::vector<Record> spare;
+    std::vector<float> lat_ms;
+    int64_t blocks = 0, dumps = 0, since_dump = 0, host_blocks = 0;
+    size_t max_pending = 0;
+};
+
+namespace {
+
+void destroy_events(xcorr_pipe *p)
+{
+    for (auto e : p->copied)
+        if (e)
+            (void)hipEventDestroy(e);
+    for (auto e : p->consumed)
+        if (e)
+            (void)hipEventDestroy(e);
+    for (auto &r : p->pending) {
+        (void)hipEventDestroy(r.begin);
+        (void)hipEventDestroy(r.end);
+    }
+    for (auto &r : p->spare) {
+        (void)hipEventDestroy(r.begin);
+        (void)hipEventDestroy(r.end);
+    }
+    p->copied.clear();
+    p->consumed.clear();
+    p->pending.clear();
+    p->spare.clear();
+}
+
+// Wait for the oldest latency record and keep its duration.
+int reap_one(xcorr_pipe *p)
+{
+    Record r = p->pending.front();
+    p->pending.pop_front();
+    hipError_t e = hipEventSynchronize(r.end);
+    float ms = 0.f;
+    if (e == hipSuccess)
+        e = hipEventElapsedTime(&ms, r.begin, r.end);
+    p->spare.push_back(r);
+    if (e != hipSuccess)
+        return hip_err(e, "latency event");
+    p->lat_ms.push_back(ms);
+    return XCORR_OK;
+}
+
+int get_record(xcorr_pipe *p, Record *out)
+{
+    if (p->pending.size() >= p->max_pending) {
+        const int rc = reap_one(p);
+        if (rc)
+            return rc;
+    }
+    if (!p->spare.empty()) {
+        *out = p->spare.back();
+        p->spare.pop_back();
+        return XCORR_OK;
+    }
+    hipError_t e = hipEventCreate(&out->begin);
+    if (e == hipSuccess) {
+        e = hipEventCreate(&out->end);
+        if (e != hipSuccess)
+            (void)hipEventDestroy(out->begin);
+    }
+    return e == hipSuccess ? XCORR_OK : hip_err(e, "hipEventCreate");
+}
+
+size_t block_bytes_of(const xcorr_ctx *ctx, int64_t block_samples)
+{
+    const xc::CtxShape c = xc::ctx_shape(ctx);
+    return (size_t)block_samples * c.n_chans * c.n_inputs * (c.sample_bits == 4 ? 1 : 2);
+}
+
+size_t round256(size_t x) { return (x + 255) / 256 * 256; }
+
+}  // namespace
+
+extern "C" {
+
+int xcorr_pipe_query(const xcorr_ctx *ctx, int n_slots, int64_t block_samples, size_t *ring_bytes)
+{
+    if (!ctx || n_slots < 1 || block_samples < 1)
+        return api_error(XCORR_E_INVAL, "ctx is NULL, n_slots < 1 or block_samples < 1");
+    if (ring_bytes)
+        *ring_bytes = (size_t)n_slots * round256(block_bytes_of(ctx, block_samples));
+    return XCORR_OK;
+}
+
+int xcorr_pipe_init(xcorr_ctx *ctx, int n_slots, int64_t block_samples, int64_t dump_every, void *d_ring,
+                    size_t ring_bytes, void *copy_stream, void *compute_stream, xcorr_pipe **out)
+{
+    size_t need = 0;
+    int rc = xcorr_pipe_query(ctx, n_slots, block_samples, &need);
+    if (rc)
+        return rc;
+    if (!out || dump_every < 1)
+        return api_error(XCORR_E_INVAL, "out is NULL or dump_every < 1");
+    if (dump_every > xc::ctx_shape(ctx).max_samples_per_dump / block_samples)
+        return api_error(XCORR_E_OVERFLOW, "dump_every blocks exceed the context's max_samples_per_dump");
+    if (n_slots > 1024)
+        return api_error(XCORR_E_INVAL, "at most 1024 ring slots");
+    if (d_ring && ((uintptr_t)d_ring % 256 || ring_bytes < need))
+        return api_error(XCORR_E_NOMEM, "ring smaller than xcorr_pipe_query's size or not 256-byte aligned");
+    xcorr_pipe *p = new (std::nothrow) xcorr_pipe();
+    if (!p)
+        return api_error(XCORR_E_NOMEM, "host allocation failed");
+    p->ctx = ctx;
+    p->n_slots = n_slots;
+    p->block_samples = block_samples;
+    p->dump_every = dump_every;
+    p->block_bytes = block_bytes_of(ctx, block_samples);
+    p->ring = static_cast<uint8_t *>(d_ring);
+    p->copy = reinterpret_cast<hipStream_t>(copy_stream);
+    p->compute = reinterpret_cast<hipStream_t>(compute_stream);
+    p->max_pending = (size_t)std::max(8, 4 * n_slots);
+    p->copied.assign(n_slots, nullptr);
+    p->consumed.assign(n_slots, nullptr);
+    p->slot_used.assign(n_slots, false);
+    for (int k = 0; k < n_slots; ++k) {
+        hipError_t e = hipEventCreateWithFlags(&p->copied[k], hipEventDisableTiming);
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(&p->consumed[k], hipEventDisableTiming);
+        if (e != hipSuccess) {
+            destroy_events(p);
+            delete p;
+            return hip_err(e, "hipEventCreate");
+        }
+    }
+    *out = p;
+    return XCORR_OK;
+}
+
+int xcorr_pipe_push(xcorr_pipe *p, const void *block, int on_host, uint64_t seq, void *d_out, int *dumped)
+{
+    if (!p || !block)
+        return api_error(XCORR_E_INVAL, "pipe or block is NULL");
+    if (on_host && !p->ring)
+        return api_error(XCORR_E_INVAL, "host blocks need a ring");
+    const bool dump_due = p->since_dump + 1 >= p->dump_every;
+    if (dump_due && !d_out)
+        return api_error(XCORR_E_INVAL, "this block completes an integration: d_out is required");
+    Record r;
+    int rc = get_record(p, &r);
+    if (rc)
+        return rc;
+    hipError_t e = hipSuccess;
+    const void *src = block;
+    if (on_host) {
+        const int k = (int)(p->host_blocks % p->n_slots);
+        uint8_t *slot = p->ring + (size_t)k * round256(p->block_bytes);
+        if (p->slot_used[k])
+            e = hipStreamWaitEvent(p->copy, p->consumed[k], 0);   // the slot's last ingest is done
+        if (e == hipSuccess)
+            e = hipEventRecord(r.begin, p->copy);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(slot, block, p->block_bytes, hipMemcpyHostToDevice, p->copy);
+        if (e == hipSuccess)
+            e = hipEventRecord(p->copied[k], p->copy);
+        if (e == hipSuccess)
+            e = hipStreamWaitEvent(p->compute, p->copied[k], 0);
+        if (e != hipSuccess) {
+            p->spare.push_back(r);
+            return hip_err(e, "block transfer");
+        }
+        src = slot;
+        rc = xcorr_ingest(p->ctx, src, p->block_samples, seq, p->compute);
+        if (rc == XCORR_OK) {
+            e = hipEventRecord(p->consumed[k], p->compute);
+            p->slot_used[k] = true;
+            ++p->host_blocks;
+        }
+    } else {
+        e = hipEventRecord(r.begin, p->compute);
+        if (e != hipSuccess) {
+            p->spare.push_back(r);
+            return hip_err(e, "hipEventRecord");
+        }
+        rc = xcorr_ingest(p->ctx, src, p->block_samples, seq, p->compute);
+    }
+    if (rc) {
+        p->spare.push_back(r);
+        return rc;
+    }
+    if (e != hipSuccess) {
+        p->spare.push_back(r);
+        return hip_err(e, "hipEventRecord");
+    }
+    ++p->blocks;
+    ++p->since_dump;
+    int did = 0;
+    if (dump_due) {
+        rc = xcorr_dump(p->ctx, d_out, nullptr, nullptr, p->compute);
+        if (rc) {
+            p->spare.push_back(r);
+            return rc;
+        }
+        p->since_dump = 0;
+        ++p->dumps;
+        did = 1;
+    }
+    e = hipEventRecord(r.end, p->compute);
+    if (e != hipSuccess) {
+        p->spare.push_back(r);
+        return hip_err(e, "hipEventRecord");
+    }
+    p->pending.push_back(r);
+    if (dumped)
+        *dumped = did;
+    return XCORR_OK;
+}
+
+int xcorr_pipe_drain(xcorr_pipe *p)
+{
+    if (!p)
+        return api_error(XCORR_E_INVAL, "pipe is NULL");
+    while (!p->pending.empty()) {
+        const int rc = reap_one(p);
+        if (rc)
+            return rc;
+    }
+    return XCORR_OK;
+}
+
+int xcorr_pipe_stats(const xcorr_pipe *p, xcorr_pipe_stats_t *out)
+{
+    if (!p || !out)
+        return api_error(XCORR_E_INVAL, "pipe or out is NULL");
+    out->blocks = p->blocks;
+    out->dumps = p->dumps;
+    out->latencies = (int64_t)p->lat_ms.size();
+    out->p50_ms = out->p99_ms = out->max_ms = out->mean_ms = 0.0;
+    if (!p->lat_ms.empty()) {
+        std::vector<float> v(p->lat_ms);
+        std::sort(v.begin(), v.end());
+        // nearest-rank percentiles
+        auto rank = [&](double q) {
+            const size_t k = (size_t)std::ceil(q * v.size());
+            return (double)v[std::min(v.size(), std::max<size_t>(k, 1)) - 1];
+        };
+        out->p50_ms = rank(0.50);
+        out->p99_ms = rank(0.99);
+        out->max_ms = v.back();
+        double s = 0;
+        for (float x : v)
+            s += x;
+        out->mean_ms = s / v.size();
+    }
+    return XCORR_OK;
+}
+
+int xcorr_pipe_reset_latency(xcorr_pipe *p)
+{
+    if (!p)
+        return api_error(XCORR_E_INVAL, "pipe is NULL");
+    const int rc = xcorr_pipe_drain(p);
+    p->lat_ms.clear();
+    return rc;
+}
+
+int xcorr_pipe_destroy(xcorr_pipe *p)
+{
+    if (!p)
+        return api_error(XCORR_E_INVAL, "pipe is NULL");
+    for (auto &r : p->pending)
+        (void)hipEventSynchronize(r.end);
+    for (int k = 0; k < p->n_slots; ++k)
+        if (p->slot_used[k])
+            (void)hipEventSynchronize(p->consumed[k]);
+    destroy_events(p);
+    delete p;
+    return XCORR_OK;
+}
+
+int xcorr_admit(const xcorr_config *cfgs, int n, const int64_t *block_samples, const int32_t *n_slots,
+                size_t budget_bytes, int32_t *admitted, size_t *used_bytes)
+{
+    if (!cfgs || n < 0 || !admitted)
+        return api_error(XCORR_E_INVAL, "cfgs or admitted is NULL, or n < 0");
+    size_t used = 0;
+    for (int a = 0; a < n; ++a) {
+        size_t ws = 0, outb = 0;
+        const int rc = xcorr_query(&cfgs[a], &ws, &outb, nullptr);
+        if (rc)
+            return rc;
+        const int64_t bs = block_samples ? block_samples[a] : 0;
+        const int slots = n_slots ? n_slots[a] : 0;
+        if (bs < 0 || slots < 0)
+            return api_error(XCORR_E_INVAL, "negative block size or slot count");
+        const size_t block = (size_t)bs * cfgs[a].n_chans * cfgs[a].n_inputs * (cfgs[a].sample_bits == 4 ? 1 : 2);
+        const size_t need = ws + round256(outb) + (size_t)slots * round256(block);
+        if (used + need <= budget_bytes) {
+            used += need;
+            admitted[a] = 1;
+        } else {
+            admitted[a] = 0;
+        }
+    }
+    if (used_bytes)
+        *used_bytes = used;
+    return XCORR_OK;
+}
+
+}  // extern "C"

@@ -69,6 +69,21 @@ class Stats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class PipeStats(ctypes.Structure):
+    _fields_ = [
+        ("blocks", ctypes.c_int64),
+        ("dumps", ctypes.c_int64),
+        ("latencies", ctypes.c_int64),
+        ("p50_ms", ctypes.c_double),
+        ("p99_ms", ctypes.c_double),
+        ("max_ms", ctypes.c_double),
+        ("mean_ms", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 _lock = threading.Lock()
 _lib = None
 
@@ -100,6 +115,15 @@ def load(path: str | None = None):
             "xcorr_batch_destroy": [vp],
             "xcorr_autotune_query": [cfgp, ctypes.POINTER(sz)],
             "xcorr_autotune": [cfgp, vp, sz, vp, ctypes.POINTER(ctypes.c_int32)],
+            "xcorr_pipe_query": [vp, ctypes.c_int, i64, ctypes.POINTER(sz)],
+            "xcorr_pipe_init": [vp, ctypes.c_int, i64, i64, vp, sz, vp, vp, ctypes.POINTER(vp)],
+            "xcorr_pipe_push": [vp, vp, ctypes.c_int, u64, vp, ctypes.POINTER(ctypes.c_int)],
+            "xcorr_pipe_drain": [vp],
+            "xcorr_pipe_stats": [vp, ctypes.POINTER(PipeStats)],
+            "xcorr_pipe_reset_latency": [vp],
+            "xcorr_pipe_destroy": [vp],
+            "xcorr_admit": [cfgp, ctypes.c_int, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_int32), sz,
+                            ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(sz)],
         }
         for name, args in sig.items():
             fn = getattr(lib, name)
@@ -243,6 +267,59 @@ def autotune(n_inputs: int, n_chans: int, sample_bits: int = 4, path: int = PATH
     return xcorr_autotune(cfg, scratch, stream)
 
 
+def xcorr_pipe_query(ctx, n_slots: int, block_samples: int) -> int:
+    rb = ctypes.c_size_t()
+    _check(load().xcorr_pipe_query(ctx, n_slots, block_samples, ctypes.byref(rb)), "xcorr_pipe_query")
+    return rb.value
+
+
+def xcorr_pipe_init(ctx, n_slots, block_samples, dump_every, ring, copy_stream, compute_stream):
+    p = ctypes.c_void_p()
+    rp = ctypes.c_void_p(ring.data_ptr()) if ring is not None else None
+    rb = ring.numel() * ring.element_size() if ring is not None else 0
+    _check(load().xcorr_pipe_init(ctx, n_slots, block_samples, dump_every, rp, rb, _stream_handle(copy_stream),
+                                  _stream_handle(compute_stream), ctypes.byref(p)), "xcorr_pipe_init")
+    return p
+
+
+def xcorr_pipe_push(pipe, block, on_host: bool, seq: int, out=None) -> bool:
+    d = ctypes.c_int()
+    _check(load().xcorr_pipe_push(pipe, ctypes.c_void_p(block.data_ptr()), int(on_host), int(seq),
+                                  ctypes.c_void_p(out.data_ptr()) if out is not None else None,
+                                  ctypes.byref(d)), "xcorr_pipe_push")
+    return bool(d.value)
+
+
+def xcorr_pipe_drain(pipe):
+    _check(load().xcorr_pipe_drain(pipe), "xcorr_pipe_drain")
+
+
+def xcorr_pipe_stats(pipe) -> dict:
+    st = PipeStats()
+    _check(load().xcorr_pipe_stats(pipe, ctypes.byref(st)), "xcorr_pipe_stats")
+    return st.as_dict()
+
+
+def xcorr_pipe_reset_latency(pipe):
+    _check(load().xcorr_pipe_reset_latency(pipe), "xcorr_pipe_reset_latency")
+
+
+def xcorr_pipe_destroy(pipe):
+    _check(load().xcorr_pipe_destroy(pipe), "xcorr_pipe_destroy")
+
+
+def xcorr_admit(cfgs, block_samples, n_slots, budget_bytes: int):
+    """(admitted flags, bytes used) for configs walked in order against a budget."""
+    n = len(cfgs)
+    arr = (Config * n)(*cfgs)
+    bs = (ctypes.c_int64 * n)(*[int(x) for x in block_samples])
+    sl = (ctypes.c_int32 * n)(*[int(x) for x in n_slots])
+    adm = (ctypes.c_int32 * n)()
+    used = ctypes.c_size_t()
+    _check(load().xcorr_admit(arr, n, bs, sl, int(budget_bytes), adm, ctypes.byref(used)), "xcorr_admit")
+    return [bool(a) for a in adm], used.value
+
+
 def xcorr_strerror(code: int) -> str:
     return load().xcorr_strerror(code).decode()
 
@@ -329,6 +406,65 @@ class Batch:
         if self.batch:
             xcorr_batch_destroy(self.batch)
             self.batch = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Pipe:
+    """Streaming loop around one Correlator: a ring of device slots for host
+    blocks, a copy stream and a compute stream (torch streams, default
+    priority), a dump every ``dump_every`` blocks, per-block latency."""
+
+    def __init__(self, correlator, block_samples: int, dump_every: int, n_slots: int = 4,
+                 host_blocks: bool = True, device="cuda"):
+        import torch
+        self.cor = correlator
+        self.block_samples = block_samples
+        self.copy_stream = torch.cuda.Stream(device=device)
+        self.compute_stream = torch.cuda.Stream(device=device)
+        self.ring = None
+        if host_blocks:
+            nbytes = xcorr_pipe_query(correlator.ctx, n_slots, block_samples)
+            self.ring = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.pipe = xcorr_pipe_init(correlator.ctx, n_slots, block_samples, dump_every, self.ring,
+                                    self.copy_stream, self.compute_stream)
+        self.seq = 0
+
+    def push(self, block, out=None, seq: int | None = None) -> bool:
+        """Submit one block (pinned host tensor or device tensor).  The pipe's
+        streams are ordered after torch's current stream (where the block, the
+        output and the ring were produced), and the tensors are recorded on
+        them so that the caching allocator does not reuse them early."""
+        import torch
+        cur = torch.cuda.current_stream()
+        self.copy_stream.wait_stream(cur)
+        self.compute_stream.wait_stream(cur)
+        if block.is_cuda:
+            block.record_stream(self.compute_stream)
+        if out is not None:
+            out.record_stream(self.compute_stream)
+        s = self.seq if seq is None else seq
+        dumped = xcorr_pipe_push(self.pipe, block, not block.is_cuda, s, out)
+        self.seq = s + 1
+        return dumped
+
+    def drain(self):
+        xcorr_pipe_drain(self.pipe)
+
+    def stats(self) -> dict:
+        return xcorr_pipe_stats(self.pipe)
+
+    def reset_latency(self):
+        xcorr_pipe_reset_latency(self.pipe)
+
+    def close(self):
+        if self.pipe:
+            xcorr_pipe_destroy(self.pipe)
+            self.pipe = None
 
     def __del__(self):
         try:

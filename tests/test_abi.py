@@ -126,3 +126,37 @@ def test_strerror_covers_codes():
     for c in (0, -1, -2, -3, -4, -5):
         assert X.xcorr_strerror(c) and X.xcorr_strerror(c) != "unknown error"
     assert X.xcorr_strerror(-99) == "unknown error"
+
+
+def test_admission_walks_arrays_in_order_against_the_budget():
+    cfgs = [X.make_config(96, 4096), X.make_config(512, 4096), X.make_config(192, 4096)]
+    bs, slots = [1024, 1024, 1024], [4, 2, 4]
+
+    def need(cfg, b, k):
+        ws, out, _ = X.xcorr_query(cfg)
+        r256 = lambda x: (x + 255) // 256 * 256
+        return ws + r256(out) + k * r256(b * cfg.n_chans * cfg.n_inputs)
+
+    n = [need(c, b, k) for c, b, k in zip(cfgs, bs, slots)]
+    adm, used = X.xcorr_admit(cfgs, bs, slots, sum(n))
+    assert adm == [True, True, True] and used == sum(n)
+    # the large array does not fit, the one after it still does
+    adm, used = X.xcorr_admit(cfgs, bs, slots, n[0] + n[2])
+    assert adm == [True, False, True] and used == n[0] + n[2]
+    adm, used = X.xcorr_admit(cfgs, bs, slots, n[0] - 1)
+    assert adm == [False, False, False] and used == 0
+    # device-resident blocks need no ring
+    adm, used = X.xcorr_admit(cfgs, bs, [0, 0, 0], 1 << 50)
+    assert used == sum(need(c, b, 0) for c, b in zip(cfgs, bs))
+
+
+def test_pipe_calls_reject_bad_arguments_on_the_host(lib):
+    rb = ctypes.c_size_t()
+    assert lib.xcorr_pipe_query(None, 4, 1024, ctypes.byref(rb)) == X.XCORR_E_INVAL
+    p = ctypes.c_void_p()
+    assert lib.xcorr_pipe_init(None, 4, 1024, 8, None, 0, None, None, ctypes.byref(p)) == X.XCORR_E_INVAL
+    assert lib.xcorr_pipe_push(None, ctypes.c_void_p(256), 0, 0, None, None) == X.XCORR_E_INVAL
+    assert lib.xcorr_pipe_drain(None) == X.XCORR_E_INVAL
+    assert lib.xcorr_pipe_stats(None, None) == X.XCORR_E_INVAL
+    assert lib.xcorr_pipe_destroy(None) == X.XCORR_E_INVAL
+    assert not p.value
