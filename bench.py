@@ -88,6 +88,203 @@ def cpu_baseline(volts_dev, n_chan_sample: int):
                       f"({cmacs:.3e} CMAC) in {dt:.2f} s wall"}
 
 
+def _timed(fn, stream, reps: int, warmup: int = 2, after=None):
+    """Mean and per-call milliseconds of fn() on `stream`, from HIP events;
+    after() (untimed) follows every call."""
+    import numpy as np
+    import torch
+    for _ in range(warmup):
+        fn()
+        if after:
+            after()
+    stream.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+        if after:
+            after()
+    stream.synchronize()
+    ms = np.array([a.elapsed_time(b) for a, b in ev])
+    return float(ms.mean()), ms
+
+
+def bench_precision8(dev, stream, reps: int) -> dict:
+    """192 inputs x 512 channels x 8192 samples of 8+8-bit noise: int8 and FP16
+    paths; the FP16 error is stated against the int8 path's exact result."""
+    import torch
+
+    from paper_2406_19013_amd import synth
+    from paper_2406_19013_amd import xcorr as X
+
+    N, F, T = 192, 512, 8192
+    with torch.cuda.stream(stream):
+        v = synth.precision8(device=dev)
+    stream.synchronize()
+    ops = OPS_PER_CMAC * N * (N + 1) // 2 * F * T
+    res, outs = {"workload": "precision-192in-512ch-8192t-8bit"}, {}
+    for name, path, peak in (("int8_mfma", X.PATH_I8_MFMA, INT8_PEAK_TOPS), ("f16_mfma", X.PATH_F16_MFMA, 2500.0)):
+        c = X.Correlator(N, F, 8, path, device=dev)
+        outs[name] = torch.empty((F, N * (N + 1) // 2, 2), dtype=torch.float32 if path == X.PATH_F16_MFMA
+                                 else torch.int32, device=dev)
+        ms, _ = _timed(lambda: c.ingest(v, T, stream=stream), stream, reps,
+                       after=lambda: c.dump(outs[name], stream=stream))
+        stream.synchronize()
+        res[name] = {"ingest_ms": ms, "tops": ops / ms / 1e9, "peak": peak, "frac": ops / ms / 1e9 / peak,
+                     "tile": c.stats()["tile"]}
+        c.close()
+    exact = outs["int8_mfma"].double()
+    d = (outs["f16_mfma"].double() - exact)
+    res["f16_max_abs_err_vs_exact"] = float(d.abs().max())
+    res["max_abs_value"] = float(exact.abs().max())
+    return res
+
+
+def bench_batched(dev, stream, reps: int) -> dict:
+    """Four arrays (64x256, 192x1024, 256x512, 512x128 inputs x channels,
+    2048 samples) in one persistent launch vs one launch per array."""
+    import torch
+
+    from paper_2406_19013_amd import synth
+    from paper_2406_19013_amd import xcorr as X
+
+    with torch.cuda.stream(stream):
+        vs = synth.batched(device=dev)
+    stream.synchronize()
+    T = vs[0].shape[0]
+    cors = [X.Correlator(N, F, 4, X.PATH_I8_MFMA, device=dev) for N, F in synth.BATCH_ARRAYS]
+    cmac = sum(N * (N + 1) // 2 * F * T for N, F in synth.BATCH_ARRAYS)
+    b = X.Batch(cors, device=dev)
+    outs = [torch.empty((F, N * (N + 1) // 2, 2), dtype=torch.int32, device=dev) for N, F in synth.BATCH_ARRAYS]
+
+    def dumps():
+        for c, o in zip(cors, outs):
+            c.dump(o, stream=stream)
+
+    batch_ms, _ = _timed(lambda: b.ingest(vs, stream=stream), stream, reps, after=dumps)
+
+    def singles():
+        for c, v in zip(cors, vs):
+            c.ingest(v, T, stream=stream)
+
+    single_ms, _ = _timed(singles, stream, reps, after=dumps)
+    stream.synchronize()
+    res = {"workload": "batched-4arrays-2048t-4bit", "arrays": [list(a) for a in synth.BATCH_ARRAYS],
+           "tiles": b.tiles, "batch_ms": batch_ms, "separate_launches_ms": single_ms,
+           "cmac_per_s": cmac / (batch_ms / 1e3), "frac_of_int8_peak": OPS_PER_CMAC * cmac / (batch_ms / 1e3) / 1e12
+           / INT8_PEAK_TOPS}
+    b.close()
+    for c in cors:
+        c.close()
+    return res
+
+
+def bench_streaming(dev, n_blocks: int, paced_blocks: int, concurrent_blocks: int) -> dict:
+    """1024-sample blocks of 4096 channels (33.55 ms of data each), a dump
+    every 128 blocks: the 192-input stream device-resident (unpaced) and from
+    pinned host memory (paced at the data rate), then 96-, 192- and
+    512-input arrays concurrently (device-resident, unpaced)."""
+    import torch
+
+    from paper_2406_19013_amd import synth
+    from paper_2406_19013_amd import xcorr as X
+
+    F, B, every, pool_n, warm = 4096, 1024, 128, 4, 64
+    span_s = B * F / BANDWIDTH_HZ
+    res = {"workload": "stream-4096ch-1024t-blocks-4bit", "block_span_ms": span_s * 1e3, "dump_every": every}
+
+    def pool_of(N, array_id):
+        return [synth.stream_block(N, F, k, array_id=array_id, device=dev) for k in range(pool_n)]
+
+    def out_of(N):
+        return torch.empty((F, N * (N + 1) // 2, 2), dtype=torch.int32, device=dev)
+
+    # 192 inputs, device-resident, unpaced
+    N = 192
+    pool = pool_of(N, 1)
+    c = X.Correlator(N, F, 4, X.PATH_I8_MFMA, device=dev)
+    out = out_of(N)
+    p = X.Pipe(c, B, every, host_blocks=False, device=dev)
+    for k in range(warm):
+        p.push(pool[k % pool_n], out=out)
+    p.drain()
+    p.reset_latency()
+    t0 = time.perf_counter()
+    for k in range(n_blocks):
+        p.push(pool[k % pool_n], out=out)
+    p.drain()
+    wall = time.perf_counter() - t0
+    st = p.stats()
+    res["n192_device_unpaced"] = {"blocks": n_blocks, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+                                  "max_ms": st["max_ms"], "rtf": n_blocks * span_s / wall, "dumps": st["dumps"]}
+    p.close()
+
+    # 192 inputs from pinned host memory through the ring, paced at the data rate
+    host_pool = [b.cpu().pin_memory() for b in pool]
+    p = X.Pipe(c, B, every, n_slots=4, host_blocks=True, device=dev)
+    c.dump(out)
+    for k in range(8):
+        p.push(host_pool[k % pool_n], out=out)
+    p.drain()
+    p.reset_latency()
+    t0 = time.perf_counter()
+    for k in range(paced_blocks):
+        due = t0 + k * span_s
+        while time.perf_counter() < due:
+            time.sleep(min(0.002, max(0.0, due - time.perf_counter())))
+        p.push(host_pool[k % pool_n], out=out)
+    p.drain()
+    st = p.stats()
+    res["n192_host_h2d_paced"] = {"blocks": paced_blocks, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+                                  "max_ms": st["max_ms"]}
+    # unpaced H2D: the rate the host link sustains
+    p.reset_latency()
+    t0 = time.perf_counter()
+    for k in range(2 * pool_n * 4):
+        p.push(host_pool[k % pool_n], out=out)
+    p.drain()
+    wall = time.perf_counter() - t0
+    res["n192_host_h2d_unpaced_rtf"] = 2 * pool_n * 4 * span_s / wall
+    p.close()
+    c.close()
+    del host_pool
+
+    # three arrays at once, each on its own pipe (own streams)
+    arrays = (96, 192, 512)
+    cfgs = [X.make_config(n, F) for n in arrays]
+    free, _ = torch.cuda.mem_get_info()
+    admitted, used = X.xcorr_admit(cfgs, [B] * 3, [0] * 3, int(free * 0.8))
+    pools = {192: pool}
+    for n, a in zip(arrays, admitted):
+        if a and n not in pools:
+            pools[n] = pool_of(n, arrays.index(n))
+    live = [n for n, a in zip(arrays, admitted) if a]
+    cs = {n: X.Correlator(n, F, 4, X.PATH_I8_MFMA, device=dev) for n in live}
+    outs = {n: out_of(n) for n in live}
+    ps = {n: X.Pipe(cs[n], B, every, host_blocks=False, device=dev) for n in live}
+    for k in range(16):
+        for n in live:
+            ps[n].push(pools[n][k % pool_n], out=outs[n])
+    for n in live:
+        ps[n].drain()
+        ps[n].reset_latency()
+    t0 = time.perf_counter()
+    for k in range(concurrent_blocks):
+        for n in live:
+            ps[n].push(pools[n][k % pool_n], out=outs[n])
+    for n in live:
+        ps[n].drain()
+    wall = time.perf_counter() - t0
+    res["concurrent"] = {"arrays": list(arrays), "admitted": admitted, "admitted_bytes": used,
+                         "blocks_per_array": concurrent_blocks, "rtf": concurrent_blocks * span_s / wall,
+                         "p99_ms": {str(n): ps[n].stats()["p99_ms"] for n in live}}
+    for n in live:
+        ps[n].close()
+        cs[n].close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +295,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-path comparison")
     ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the precision, batched and streaming workloads")
+    ap.add_argument("--stream-blocks", type=int, default=2048)
+    ap.add_argument("--paced-blocks", type=int, default=64)
+    ap.add_argument("--concurrent-blocks", type=int, default=128)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the X-engine shards by channel with no cross-GPU "
@@ -200,7 +402,16 @@ def main():
                      "hbm_frac": (in_bytes + acc_bytes) / ingest_s / 1e9 / HBM_PEAK_GBS},
     }
     mf.close()
+    if not args.no_extra:
+        del volts
+        result["precision8"] = bench_precision8(dev, stream, max(5, args.steps // 2))
+        result["batched"] = bench_batched(dev, stream, max(5, args.steps // 2))
+        result["streaming"] = bench_streaming(dev, args.stream_blocks, args.paced_blocks, args.concurrent_blocks)
+        result["latency_ms"]["p99_block_stream"] = result["streaming"]["n192_device_unpaced"]["p99_ms"]
     if not args.no_cpu:
+        with torch.cuda.stream(stream):
+            volts = synth.tianlai(device=dev)
+        stream.synchronize()
         result["cpu_baseline"] = cpu_baseline(volts, args.cpu_channels)
     print(json.dumps(result), flush=True)
 
