@@ -35,16 +35,9 @@ OPS_PER_CMAC = 8              # one complex multiply-accumulate = 4 real MACs
 PROFILES = os.path.join(ROOT, "profiles")
 
 
-# sources of the dominant kernel (xc_mfma4_kernel); counters taken on other
-# sources are not reported
-KERNEL_SOURCES = ("xcorr_mfma4.hip", "xc_mfma.h", "xc_device.h")
-
-
 def kernel_source_sha() -> str:
-    h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
-        h.update(open(os.path.join(ROOT, "paper_2406_19013_amd", "csrc", name), "rb").read())
-    return h.hexdigest()[:16]
+    from paper_2406_19013_amd.profsum import kernel_source_sha as sha
+    return sha()
 
 
 def measured_traffic(per_launch_algo_bytes: float):

@@ -1,0 +1,28 @@
+"""The compiler's resource report of the last build: the kernels on the hot
+paths (16-byte-aligned inputs, 64-row chunks) must not spill registers to
+scratch memory; a spill there costs an order of magnitude in time."""
+import os
+import re
+
+import pytest
+
+from paper_2406_19013_amd import build
+
+REPORT = os.path.join(os.path.dirname(build.__file__), "_build", build.RESOURCES)
+
+HOT = [
+    re.compile(r"xc_mfma4_kernelILi\dELi64ELi1E"),        # 4+4-bit, every D, LDS-DMA
+    re.compile(r"xc_mfma8_kernelILi\dELb[01]ELi64ELi1E"),  # 8+8-bit int8 and FP16, LDS-DMA
+    re.compile(r"xc_batch4_kernelILi1E"),                  # batched, LDS-DMA
+]
+
+
+@pytest.mark.skipif(not os.path.exists(REPORT), reason="no build report (run the build first)")
+def test_hot_kernels_do_not_spill():
+    res = build.read_resources(REPORT)
+    hot = {k: v for k, v in res.items() if any(p.search(k) for p in HOT)}
+    assert len(hot) >= 6 + 12 + 1, sorted(hot)
+    spills = {k: v["ScratchSize"] for k, v in hot.items() if v.get("ScratchSize", 0)}
+    assert not spills, spills
+    for k, v in hot.items():
+        assert v["VGPRs"] + v.get("AGPRs", 0) <= 512, k
