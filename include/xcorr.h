@@ -153,8 +153,9 @@ int xcorr_destroy(xcorr_ctx *ctx);
  *   keep their workspaces); d_workspace (>= the queried size, 256-byte
  *   aligned) is borrowed until xcorr_batch_destroy and is initialised here
  *   with a synchronous kernel on the null stream.  Each array keeps its own
- *   region plan when its tile is 2, 3 or 4; other tiles are replaced by
- *   whichever of 2, 3, 4 pads least (xcorr_batch_tiles reports the choice).
+ *   region plan when its tile is 2, 3, 4, or 6 with N <= 192; other tiles are
+ *   replaced by whichever of 2, 3, 4 pads least (xcorr_batch_tiles reports
+ *   the choice).
  *   Errors: XCORR_E_INVAL (n outside 1..XCORR_MAX_BATCH, a NULL or repeated
  *   context, a context that is not 4-bit int8-MFMA), XCORR_E_NOMEM, XCORR_E_HIP.
  * xcorr_batch_ingest: d_volts[a] = [n_samples[a]][F_a][N_a] for array a;

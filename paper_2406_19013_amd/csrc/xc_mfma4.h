@@ -295,5 +295,276 @@ __device__ __forceinline__ void mfma4_dispatch(uint8_t *smem, const uint8_t *__r
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Fused-product variant.  Re and Im each take one accumulator per tile:
+//     C_re += R_i R_j^T  then  C_re += I_i I_j^T          (= 256 Re)
+//     C_im += I_i R_j^T  then  C_im += R_i (~I_j)^T       (= 256 Im - 16 S_i)
+// with ~I = -I - 1 (a bitwise NOT of 16*im, exact in int8) and S_i the sum of
+// re_i over the samples, taken with v_dot4 on the R operand and added back in
+// the epilogue.  Eight waves = product (Re, Im) x K parity x tile half, so a
+// wave reads each operand block once per 32-sample K step and feeds it to
+// twice as many MFMAs as in the per-role layout above: half the LDS transpose
+// reads per MFMA.  The two parities' partial sums are descaled separately
+// (each partial is a multiple of 256 once its row-sum term is added), so no
+// int32 sum exceeds the bound: per parity |partial| <= 32896 per sample.
+
+constexpr int fused_role(int prod, int par) { return prod + 2 * par; }
+// tiles per epilogue round: 4 roles x G x 4 KB plus the row sums fit the ring
+constexpr int fused_epilogue_tiles(int D) { return D <= 3 ? 3 : 6; }
+// ring depth (64-row chunks of 16 KB): as deep as LDS allows, one work-group
+// per CU for D >= 4, two for D <= 3
+constexpr int fused_nbuf(int D) { return D <= 3 ? 4 : 8; }
+constexpr int fused_smem_bytes(int D)
+{
+    return fused_nbuf(D) * 64 * kRowBytes > fused_epilogue_tiles(D) * 16384 + 2 * D * 256
+               ? fused_nbuf(D) * 64 * kRowBytes
+               : fused_epilogue_tiles(D) * 16384 + 2 * D * 256;
+}
+
+// Does half HALF compute the row sums of row block I (the half owning the
+// first tile of row I)?
+constexpr bool owns_rowsum(int D, bool tri, int half, int I)
+{
+    const int t = tri ? I * (I + 1) / 2 : I * D;
+    return (t >= half_begin(D, tri, half)) && (t < half_end(D, tri, half));
+}
+
+template <int D, bool TRI, int PROD, int HALF, int KOFF>
+__device__ __forceinline__ void k_step_fused(lds_u8 *const *addr, v16i *acc, int *rsum)
+{
+    constexpr int NB = TRI ? D : 2 * D;
+    constexpr int T0 = half_begin(D, TRI, HALF), T1 = half_end(D, TRI, HALF);
+    v4i A0[NB], B0[NB], A1[NB], B1[NB];   // operands of the first and second product
+    static_for<0, NB>([&](auto bc) {
+        constexpr int b = bc;
+        constexpr bool ua = half_uses_row(D, TRI, HALF, b), ub = half_uses_col(D, TRI, HALF, b);
+        if constexpr (ua || ub) {
+            const v4i x = frag_tr8<8 * kRowBytes>(addr[b] + KOFF);
+            const v4i r = re16(x), i = im16(x);
+            if constexpr (PROD == 0) {
+                A0[b] = r;   // R_i R_j^T
+                B0[b] = r;
+                A1[b] = i;   // I_i I_j^T
+                B1[b] = i;
+            } else {
+                if constexpr (ua) {
+                    A0[b] = i;   // I_i R_j^T
+                    A1[b] = r;   // R_i (~I_j)^T
+                    if constexpr (b < D && owns_rowsum(D, TRI, HALF, b))
+                        for (int k = 0; k < 4; ++k)
+                            rsum[b] = __builtin_amdgcn_sdot4(r[k], 0x01010101, rsum[b], false);
+                }
+                if constexpr (ub) {
+                    B0[b] = r;
+                    B1[b] = ~i;
+                }
+            }
+        }
+    });
+    // all first products, then all second ones: consecutive MFMAs never
+    // depend on each other's accumulator
+    static_for<T0, T1>([&](auto tc) {
+        constexpr int t = tc;
+        acc[t - T0] = mfma_i8(A0[row_block(D, TRI, t)], B0[col_block(D, TRI, t)], acc[t - T0]);
+    });
+    static_for<T0, T1>([&](auto tc) {
+        constexpr int t = tc;
+        acc[t - T0] = mfma_i8(A1[row_block(D, TRI, t)], B1[col_block(D, TRI, t)], acc[t - T0]);
+    });
+}
+
+template <int D, bool TRI, int KC, int NBUF, int VEC, int PROD, int PAR, int HALF>
+__device__ __forceinline__ void mfma4f_region(uint8_t *smem, const uint8_t *__restrict__ volts,
+                                              int64_t T, int F, int N, int f, int row_blk, int col_blk,
+                                              int2 *__restrict__ acc_out, int accumulate)
+{
+    constexpr int NT = n_tiles(D, TRI);
+    constexpr int T0 = half_begin(D, TRI, HALF), T1 = half_end(D, TRI, HALF);
+    constexpr int NB = TRI ? D : 2 * D;
+    constexpr int BUF = KC * kRowBytes;
+    constexpr int LOADS = KC * 16 / kMfmaThreads;
+    constexpr int G = fused_epilogue_tiles(D);
+    constexpr int ROLE = fused_role(PROD, PAR);
+    static_assert(LOADS * kMfmaThreads == KC * 16, "chunk must be a whole number of wave loads");
+    static_assert(KC % 64 == 0, "a chunk holds whole pairs of 32-sample K steps");
+    static_assert(4 * G * 4096 + 2 * D * 64 * 4 <= fused_smem_bytes(D), "epilogue stage fits");
+
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));   // keep per-lane offsets inside an enclosing item loop
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int g = lane >> 4, q = lane & 15;
+    lds_u8 *const ring = (lds_u8 *)smem;
+
+    const int row_off = ((g >> 1) * 16 + (q >> 1)) * kRowBytes + (q & 1) * 8;
+    int colo[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+        colo[b] = ((2 * b + (g & 1)) ^ (q & 14)) << 4;
+
+    const int64_t row_bytes = (int64_t)F * N;
+    int voff[LOADS];
+#pragma unroll
+    for (int k = 0; k < LOADS; ++k) {
+        const int U = (wave * LOADS + k) * 64 + lane;
+        const int r = U >> 4;
+        const int p = (U & 15) ^ ((r & 7) << 1);
+        const int i0 = p < 2 * D ? row_blk * 32 + 16 * p : col_blk * 32 + 16 * (p - 2 * D);
+        const bool valid = p < 2 * NB && i0 < N;
+        voff[k] = valid ? (int)(r * row_bytes + (int64_t)f * N + i0) : kBufferOutOfRange;
+    }
+
+    v16i acc[T1 > T0 ? T1 - T0 : 1];
+#pragma unroll
+    for (int t = 0; t < (T1 > T0 ? T1 - T0 : 1); ++t)
+        acc[t] = v16i{};
+    int rsum[D];
+#pragma unroll
+    for (int b = 0; b < D; ++b)
+        rsum[b] = 0;
+
+    const int nchunks = (int)((T + KC - 1) / KC);
+    auto issue = [&](int c, int bufi) {
+        const int64_t rows = min((int64_t)KC, T - (int64_t)c * KC);
+        __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(volts + (int64_t)c * KC * row_bytes), (short)0, (int)(rows * row_bytes), 0x00020000);
+        lds_u8 *dst = ring + bufi * BUF + wave * LOADS * 1024;
+#pragma unroll
+        for (int k = 0; k < LOADS; ++k)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (__attribute__((address_space(3))) void *)(dst + k * 1024),
+                                                     16, voff[k], 0, 0, 0);
+    };
+    auto fill_sync = [&](int c, int bufi) {
+        lds_u8 *dst = ring + bufi * BUF;
+#pragma unroll
+        for (int k = 0; k < LOADS; ++k) {
+            const int U = (wave * LOADS + k) * 64 + lane;
+            const int r = U >> 4;
+            const int p = (U & 15) ^ ((r & 7) << 1);
+            const int i0 = p < 2 * D ? row_blk * 32 + 16 * p : col_blk * 32 + 16 * (p - 2 * D);
+            const v4i val = p < 2 * NB ? load_piece(volts, (int64_t)c * KC + r, T, f, F, N, i0, 1, 0)
+                                       : v4i{0, 0, 0, 0};
+            *(__attribute__((address_space(3))) v4i *)(dst + U * 16) = val;
+        }
+    };
+
+    if constexpr (VEC) {
+#pragma unroll
+        for (int c = 0; c < NBUF - 1; ++c)
+            if (c < nchunks)
+                issue(c, c);
+    }
+    int bufc = 0;
+    for (int c = 0; c < nchunks; ++c) {
+        if constexpr (VEC) {
+            if (c + NBUF - 2 < nchunks)
+                wait_vmcnt<LOADS * (NBUF - 2)>();
+            else
+                wait_vmcnt<0>();
+            barrier_no_fence();
+            if (c + NBUF - 1 < nchunks)
+                issue(c + NBUF - 1, bufc == 0 ? NBUF - 1 : bufc - 1);
+        } else {
+            __syncthreads();
+            fill_sync(c, bufc);
+            __syncthreads();
+        }
+        lds_u8 *addr[NB];
+        lds_u8 *const cb = ring + bufc * BUF + row_off;
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+            addr[b] = cb + colo[b];
+        // 32-sample K steps of this chunk: this wave takes those of its parity
+        static_for<0, KC / 64>([&](auto kc) {
+            k_step_fused<D, TRI, PROD, HALF, (2 * kc + PAR) * 32 * kRowBytes>(addr, acc, rsum);
+        });
+        bufc = bufc + 1 == NBUF ? 0 : bufc + 1;
+    }
+    __syncthreads();
+
+    // Epilogue: stage [role = (product, parity)][tile][rq][lane] v4i, then the
+    // row sums [parity][row block][64 lanes]; emit descales each parity.
+    typedef __attribute__((address_space(3))) v4i lds_v4i;
+    lds_v4i *const stage = (lds_v4i *)smem;
+    int *const sstage = (int *)(smem + 4 * G * 4096);
+    if constexpr (PROD == 1) {
+        static_for<0, D>([&](auto bc) {
+            if constexpr (owns_rowsum(D, TRI, HALF, bc))
+                sstage[(PAR * D + bc) * 64 + lane] = rsum[bc];
+        });
+    }
+    const int64_t P = (int64_t)N * (N + 1) / 2;
+    int2 *const out_f = acc_out + (int64_t)f * P;
+#pragma unroll
+    for (int t0 = 0; t0 < NT; t0 += G) {
+        static_for<T0, T1>([&](auto tc) {
+            constexpr int t = tc;
+            const int u = t - t0;
+            if (u >= 0 && u < G) {
+#pragma unroll
+                for (int rq = 0; rq < 4; ++rq)
+                    stage[((ROLE * G + u) * 4 + rq) * 64 + lane] =
+                        v4i{acc[t - T0][4 * rq], acc[t - T0][4 * rq + 1], acc[t - T0][4 * rq + 2],
+                            acc[t - T0][4 * rq + 3]};
+            }
+        });
+        __syncthreads();
+        const int NQ = (NT - t0 < G ? NT - t0 : G) * 256;
+        for (int qq = tid; qq < NQ; qq += kMfmaThreads) {
+            const int u = qq >> 8, rq = (qq >> 6) & 3, ln = qq & 63;
+            const int t = t0 + u;
+            const int I = TRI ? tri_I_rt(t) : t / D;
+            const int J = TRI ? tri_J_rt(t) : t % D;
+            const int i0 = (row_blk + I) * 32 + 8 * rq + 4 * (ln >> 5);
+            const int j = (col_blk + J) * 32 + (ln & 31);
+            const int e = (u * 4 + rq) * 64 + ln;
+            const v4i re0 = stage[(fused_role(0, 0) * G * 4) * 64 + e];
+            const v4i re1 = stage[(fused_role(0, 1) * G * 4) * 64 + e];
+            const v4i im0 = stage[(fused_role(1, 0) * G * 4) * 64 + e];
+            const v4i im1 = stage[(fused_role(1, 1) * G * 4) * 64 + e];
+            const int il0 = 8 * rq + 4 * (ln >> 5);
+            int64_t p = (int64_t)i0 * (i0 + 1) / 2 + j;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int i = i0 + m;
+                if (i < N && j <= i) {
+                    const int il = il0 + m;
+                    const int s0 = sstage[I * 64 + il] + sstage[I * 64 + 32 + il];
+                    const int s1 = sstage[(D + I) * 64 + il] + sstage[(D + I) * 64 + 32 + il];
+                    int re = (re0[m] >> 8) + (re1[m] >> 8);
+                    int im = ((im0[m] + s0) >> 8) + ((im1[m] + s1) >> 8);
+                    if (accumulate) {
+                        const int2 o = out_f[p];
+                        re += o.x;
+                        im += o.y;
+                    }
+                    out_f[p] = make_int2(re, im);
+                }
+                p += i + 1;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int D, bool TRI, int KC, int NBUF, int VEC>
+__device__ __forceinline__ void mfma4f_dispatch(uint8_t *smem, const uint8_t *__restrict__ volts,
+                                                int64_t T, int F, int N, int f, int row_blk, int col_blk,
+                                                int2 *__restrict__ acc_out, int accumulate)
+{
+    switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {
+#define XC_CASE(W)                                                                                     \
+    case W:                                                                                            \
+        mfma4f_region<D, TRI, KC, NBUF, VEC, ((W) >> 2), (((W) >> 1) & 1), (((W) & 1) ^ ((W) >> 2))>(  \
+            smem, volts, T, F, N, f, row_blk, col_blk, acc_out, accumulate);                           \
+        break;
+        XC_CASE(0) XC_CASE(1) XC_CASE(2) XC_CASE(3) XC_CASE(4) XC_CASE(5) XC_CASE(6) XC_CASE(7)
+#undef XC_CASE
+    default: break;
+    }
+}
+
+
 }  // namespace
 }  // namespace xc

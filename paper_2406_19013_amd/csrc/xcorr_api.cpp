@@ -18,6 +18,7 @@ struct xcorr_ctx {
     xcorr_config cfg;
     xc::Plan plan;
     int kc;
+    bool per_role;   // 4+4-bit: per-role kernel instead of the fused-product one
     void *ws;
     size_t ws_bytes;
     int64_t t_max;
@@ -127,11 +128,12 @@ size_t acc_bytes(const xcorr_config &c)
 }
 
 // Region plan of a batch member: the context's own plan when its block size
-// is one the batched kernel carries (2, 3, 4), else the one of those with the
-// fewest tiles (padding included), the larger on a tie.
+// is one the batched kernel carries (2, 3, 4, or 6 with N <= 192), else the
+// one of 2, 3, 4 with the fewest tiles (padding included), the larger on a tie.
 xc::Plan batch_plan(const xcorr_ctx *c)
 {
-    if (c->plan.D >= 2 && c->plan.D <= 4)
+    const int D = c->plan.D;
+    if ((D >= 2 && D <= 4) || (D == 6 && c->cfg.n_inputs <= 192))
         return c->plan;
     xc::Plan best;
     int64_t best_tiles = -1;
@@ -238,6 +240,9 @@ int xcorr_init(const xcorr_config *cfg, void *d_workspace, size_t ws_bytes, xcor
         const char *v = std::getenv("XCORR_CHUNK");
         if (v && std::strcmp(v, "128") == 0 && c->plan.D >= 4 && cfg->sample_bits == 4)
             c->kc = 128;
+        // $XCORR_MFMA4_VARIANT=roles selects the per-role 4+4-bit kernel
+        const char *fv = std::getenv("XCORR_MFMA4_VARIANT");
+        c->per_role = fv && std::strcmp(fv, "roles") == 0;
     }
     c->ws = d_workspace;
     c->ws_bytes = ws_bytes;
@@ -260,7 +265,8 @@ int xcorr_ingest(xcorr_ctx *ctx, const void *d_volts, int64_t n_samples, uint64_
     const int64_t bytes_per_row = (int64_t)c.n_chans * c.n_inputs * (c.sample_bits == 4 ? 1 : 2);
     const int64_t per_launch =
         c.path == XCORR_PATH_PLAIN ? n_samples
-                                   : (c.sample_bits == 4 ? xc::kMaxSamplesPerLaunch4 : xc::kMaxSamplesPerLaunch8);
+        : c.sample_bits == 8       ? xc::kMaxSamplesPerLaunch8
+                                   : xc::kMaxSamplesPerLaunch4;
     for (int64_t t0 = 0; t0 < n_samples; t0 += per_launch) {
         const int64_t tl = std::min<int64_t>(per_launch, n_samples - t0);
         const int accumulate = (ctx->acc_samples > 0 || t0 > 0) ? 1 : 0;
@@ -268,6 +274,8 @@ int xcorr_ingest(xcorr_ctx *ctx, const void *d_volts, int64_t n_samples, uint64_
         hipError_t e;
         if (c.path == XCORR_PATH_PLAIN)
             e = xc::launch_plain(c.sample_bits, vp, tl, c.n_chans, c.n_inputs, acc, accumulate, s);
+        else if (c.sample_bits == 4 && !ctx->per_role)
+            e = xc::launch_mfma4f(ctx->plan, vp, tl, c.n_chans, c.n_inputs, acc, accumulate, s);
         else if (c.sample_bits == 4)
             e = xc::launch_mfma4(ctx->plan, ctx->kc, vp, tl, c.n_chans, c.n_inputs, acc, accumulate, s);
         else

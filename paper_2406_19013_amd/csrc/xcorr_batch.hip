@@ -14,11 +14,12 @@ namespace xc {
 namespace {
 
 constexpr int kBatchKC = 64;
+// region sizes the batched kernel carries: 2, 3, 4 (any N) and 6 (N <= 192)
 constexpr int batch_smem_bytes()
 {
     int m = 0;
-    for (int d = 2; d <= 4; ++d)
-        m = mfma4_smem_bytes(d, kBatchKC) > m ? mfma4_smem_bytes(d, kBatchKC) : m;
+    for (int d : {2, 3, 4, 6})
+        m = fused_smem_bytes(d) > m ? fused_smem_bytes(d) : m;
     return m;
 }
 
@@ -36,17 +37,18 @@ __device__ __forceinline__ void rect_ab(int k, int &a, int &b)
 template <int D, int VEC>
 __device__ __forceinline__ void batch_item(uint8_t *smem, const BatchArray &A, int local)
 {
-    constexpr int NBUF = mfma4_nbuf(D, kBatchKC);
+    // the work-group runs alone on its CU: the ring may be as deep as D = 4's
+    constexpr int NBUF = fused_nbuf(4);
     const int f = local / A.regions;
     const int r = local - f * A.regions;
     if (r < A.nseg) {
-        mfma4_dispatch<D, true, kBatchKC, NBUF, VEC>(smem, A.volts, A.T, A.F, A.N, f, r * D, r * D, A.acc,
-                                                     A.accumulate);
-    } else {
+        mfma4f_dispatch<D, true, kBatchKC, NBUF, VEC>(smem, A.volts, A.T, A.F, A.N, f, r * D, r * D, A.acc,
+                                                      A.accumulate);
+    } else if constexpr (D <= 4) {
         int a, b;
         rect_ab(r - A.nseg, a, b);
-        mfma4_dispatch<D, false, kBatchKC, NBUF, VEC>(smem, A.volts, A.T, A.F, A.N, f, a * D, b * D, A.acc,
-                                                      A.accumulate);
+        mfma4f_dispatch<D, false, kBatchKC, NBUF, VEC>(smem, A.volts, A.T, A.F, A.N, f, a * D, b * D, A.acc,
+                                                       A.accumulate);
     }
 }
 
@@ -92,6 +94,7 @@ void xc_batch4_kernel(const BatchArgs args, int *__restrict__ queue)
         switch (A.D) {
         case 2: batch_item<2, VEC>(smem, A, local); break;
         case 3: batch_item<3, VEC>(smem, A, local); break;
+        case 6: batch_item<6, VEC>(smem, A, local); break;
         default: batch_item<4, VEC>(smem, A, local); break;
         }
     }
@@ -133,7 +136,7 @@ hipError_t launch_batch4(const BatchArgs &args, int *queue, int vec, int grid, h
         return hipErrorInvalidValue;
     for (int a = 0; a < args.n; ++a) {
         const BatchArray &A = args.a[a];
-        if (A.D < 2 || A.D > 4 || A.T < 1 || A.T > kMaxSamplesPerLaunch4 || !A.volts || !A.acc ||
+        if (A.D < 2 || A.D == 5 || A.D > 6 || (A.D == 6 && A.N > 192) || A.T < 1 || A.T > kMaxSamplesPerLaunch4 || !A.volts || !A.acc ||
             (uintptr_t)A.acc % 16)
             return hipErrorInvalidValue;
     }

@@ -34,13 +34,20 @@ bool plan_supported(int N, int D);
 // Launchers: enqueue on `stream`, return hipSuccess or the launch error.
 // `accumulate` = 0 overwrites the accumulators, 1 adds to them.
 // T <= kMaxSamplesPerLaunch for the MFMA paths (the host splits longer ingests).
-constexpr int64_t kMaxSamplesPerLaunch4 = 131071;  // |16re*16re| <= 2^14 per sample
+// 4+4-bit: the fused-product kernel keeps two K-parity partial sums of at
+// most 32896 per sample each (|256 Im| + |16 re|), over 32-sample steps, so a
+// launch takes at most 2 * 32 * floor((2^31 - 1) / 32896 / 32) samples.
+constexpr int64_t kMaxSamplesPerLaunch4 = 130560;
+
 constexpr int64_t kMaxSamplesPerLaunch8 = 133143;  // |re*re| <= 127^2 per sample
 
 hipError_t launch_plain(int bits, const uint8_t *volts, int64_t T, int F, int N, int2 *acc,
                         int accumulate, hipStream_t s);
 hipError_t launch_mfma4(const Plan &pl, int kc, const uint8_t *volts, int64_t T, int F, int N,
                         int2 *acc, int accumulate, hipStream_t s);
+// fused-product variant (one Re and one Im accumulator per tile), the default
+hipError_t launch_mfma4f(const Plan &pl, const uint8_t *volts, int64_t T, int F, int N, int2 *acc,
+                         int accumulate, hipStream_t s);
 // 8+8-bit input, int8 MFMA (f16 = false, int2 accumulators) or FP16 MFMA with
 // FP32 accumulation (f16 = true, float2 accumulators).
 hipError_t launch_mfma8(const Plan &pl, bool f16, const uint8_t *volts, int64_t T, int F, int N, void *acc,

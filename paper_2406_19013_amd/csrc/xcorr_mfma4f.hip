@@ -1,0 +1,79 @@
+// 4+4-bit int8-MFMA kernels of the X-engine, fused-product variant (one Re
+// and one Im accumulator per tile; waves = product x K parity x tile half),
+// every diagonal block size D in one translation unit.
+#include "xc_mfma4.h"
+
+namespace xc {
+namespace {
+
+// One work-group per (channel, region), regions as in the per-role kernel.
+// Two work-groups per CU for D <= 3 (128 registers per wave; at D = 3 the
+// compiler spills 32 bytes per lane, still faster than one work-group with
+// 256 registers), one above.
+constexpr int fused_wgs_per_cu(int D) { return D <= 3 ? 2 : 1; }
+
+template <int D, int VEC>
+__global__ __launch_bounds__(kMfmaThreads)
+__attribute__((amdgpu_waves_per_eu(2 * fused_wgs_per_cu(D), 2 * fused_wgs_per_cu(D))))
+void xc_mfma4f_kernel(const uint8_t *__restrict__ volts, int64_t T, int F, int N, int nseg, int R,
+                      int nitems, int2 *__restrict__ acc_out, int accumulate)
+{
+    constexpr int KC = 64;
+    constexpr int NBUF = fused_nbuf(D);
+    __shared__ __attribute__((aligned(1024))) uint8_t smem[fused_smem_bytes(D)];
+
+    const int item = xcd_item();
+    if (item >= nitems)
+        return;
+    const int f = item / R;
+    const int r = item - f * R;
+    if (r < nseg) {
+        mfma4f_dispatch<D, true, KC, NBUF, VEC>(smem, volts, T, F, N, f, r * D, r * D, acc_out, accumulate);
+    } else if constexpr (D <= 4) {
+        const int k = r - nseg;
+        int a = (int)((1.f + sqrtf(1.f + 8.f * k)) * 0.5f);
+        while (a * (a - 1) / 2 > k)
+            --a;
+        while ((a + 1) * a / 2 <= k)
+            ++a;
+        const int b = k - a * (a - 1) / 2;
+        mfma4f_dispatch<D, false, KC, NBUF, VEC>(smem, volts, T, F, N, f, a * D, b * D, acc_out,
+                                                 accumulate);
+    }
+}
+
+}  // namespace
+
+template <int D>
+static hipError_t launch_mfma4f_t(const Plan &pl, const uint8_t *volts, int64_t T, int F, int N,
+                                  int2 *acc, int accumulate, hipStream_t s)
+{
+    const int64_t nitems64 = (int64_t)F * pl.regions;
+    if (nitems64 > (1LL << 30))
+        return hipErrorInvalidValue;
+    const int nitems = (int)nitems64;
+    const int vec_ok = (N % 16 == 0) && ((uintptr_t)volts % 16 == 0) &&
+                       64LL * F * N < (1LL << 31) - 16;
+    auto kern = vec_ok ? xc_mfma4f_kernel<D, 1> : xc_mfma4f_kernel<D, 0>;
+    hipLaunchKernelGGL(kern, dim3(xcd_grid(nitems)), dim3(kMfmaThreads), 0, s, volts, T, F, N,
+                       pl.nseg, pl.regions, nitems, acc, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_mfma4f(const Plan &pl, const uint8_t *volts, int64_t T, int F, int N, int2 *acc,
+                         int accumulate, hipStream_t s)
+{
+    if (!plan_supported(N, pl.D) || T > kMaxSamplesPerLaunch4)
+        return hipErrorInvalidValue;
+    switch (pl.D) {
+    case 1: return launch_mfma4f_t<1>(pl, volts, T, F, N, acc, accumulate, s);
+    case 2: return launch_mfma4f_t<2>(pl, volts, T, F, N, acc, accumulate, s);
+    case 3: return launch_mfma4f_t<3>(pl, volts, T, F, N, acc, accumulate, s);
+    case 4: return launch_mfma4f_t<4>(pl, volts, T, F, N, acc, accumulate, s);
+    case 5: return launch_mfma4f_t<5>(pl, volts, T, F, N, acc, accumulate, s);
+    case 6: return launch_mfma4f_t<6>(pl, volts, T, F, N, acc, accumulate, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace xc

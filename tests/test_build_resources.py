@@ -1,6 +1,8 @@
 """The compiler's resource report of the last build: the kernels on the hot
 paths (16-byte-aligned inputs, 64-row chunks) must not spill registers to
-scratch memory; a spill there costs an order of magnitude in time."""
+scratch memory; a spill there has cost an order of magnitude in time.  (The
+fused 4+4-bit kernel at D = 3 runs two work-groups per CU with a 32-byte
+spill, measured faster than one work-group without it, and is left out.)"""
 import os
 import re
 
@@ -11,7 +13,8 @@ from paper_2406_19013_amd import build
 REPORT = os.path.join(os.path.dirname(build.__file__), "_build", build.RESOURCES)
 
 HOT = [
-    re.compile(r"xc_mfma4_kernelILi\dELi64ELi1E"),        # 4+4-bit, every D, LDS-DMA
+    re.compile(r"xc_mfma4f_kernelILi[124-6]ELi1E"),       # 4+4-bit default kernel, LDS-DMA
+    re.compile(r"xc_mfma4_kernelILi\dELi64ELi1E"),        # 4+4-bit per-role kernel, every D
     re.compile(r"xc_mfma8_kernelILi\dELb[01]ELi64ELi1E"),  # 8+8-bit int8 and FP16, LDS-DMA
     re.compile(r"xc_batch4_kernelILi1E"),                  # batched, LDS-DMA
 ]
@@ -21,7 +24,7 @@ HOT = [
 def test_hot_kernels_do_not_spill():
     res = build.read_resources(REPORT)
     hot = {k: v for k, v in res.items() if any(p.search(k) for p in HOT)}
-    assert len(hot) >= 6 + 12 + 1, sorted(hot)
+    assert len(hot) >= 5 + 6 + 12 + 1, sorted(hot)
     spills = {k: v["ScratchSize"] for k, v in hot.items() if v.get("ScratchSize", 0)}
     assert not spills, spills
     for k, v in hot.items():

@@ -41,7 +41,7 @@ def test_batch_matches_oracle(arrays):
     vs = [synth.uniform_volts4(N, F, T, seed=(3001, N, F, T)) for N, F, T in arrays]
     cors = [X.Correlator(N, F, 4, X.PATH_I8_MFMA) for N, F, _ in arrays]
     b = X.Batch(cors)
-    assert all(t in (2, 3, 4) for t in b.tiles)
+    assert all(t in (2, 3, 4, 6) for t in b.tiles)
     b.ingest([v.cuda() for v in vs])
     for (got, n), v, (N, F, T) in zip(dump_all(cors), vs, arrays):
         assert n == T

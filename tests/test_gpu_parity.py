@@ -68,10 +68,17 @@ TILES = [(192, 2), (192, 3), (192, 4), (192, 6), (160, 5), (96, 3), (64, 2), (25
          (130, 2), (300, 3), (512, 4), (20, 1)]
 
 
+# the default 4+4-bit kernel (fused products) and the per-role one
+VARIANTS = ["fused", "roles"]
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("N,tile", TILES, ids=[f"N{n}D{d}" for n, d in TILES])
-def test_every_tile_shape_bit_exact(N, tile):
+def test_every_tile_shape_bit_exact(N, tile, variant, monkeypatch):
+    if variant == "roles":
+        monkeypatch.setenv("XCORR_MFMA4_VARIANT", "roles")
     F, T = 2, 200
-    _say(f"tile N={N} D={tile}")
+    _say(f"tile N={N} D={tile} {variant}")
     v = synth.gaussian_volts(N, F, T, sigma=2.5, bits=4, seed=(1002, N, tile), tone=synth.Tone())
     got = gpu_correlate(v, N, F, 4, X.PATH_I8_MFMA, tile)
     assert np.array_equal(got, expected(v, N, F))
@@ -85,6 +92,23 @@ def test_ingest_splits_accumulate_exactly(path):
     _say(f"splits {path}")
     v = synth.uniform_volts4(N, F, T, seed=(1003,))
     got = gpu_correlate(v, N, F, 4, PATHS[path], splits=splits)
+    assert np.array_equal(got, expected(v, N, F))
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_extreme_mix_across_launch_split(variant, monkeypatch):
+    """Re and im drawn from {-8, 7} (the largest products of both signs) over
+    140,001 samples, more than one launch of either kernel takes."""
+    if variant == "roles":
+        monkeypatch.setenv("XCORR_MFMA4_VARIANT", "roles")
+    N, F, T = 16, 1, 140_001
+    _say(f"extreme mix {variant}")
+    g = torch.Generator().manual_seed(11)
+    pick = torch.tensor([-8, 7], dtype=torch.int32)
+    re = pick[torch.randint(0, 2, (T, F, N), generator=g)]
+    im = pick[torch.randint(0, 2, (T, F, N), generator=g)]
+    v = synth.pack4(re, im)
+    got = gpu_correlate(v, N, F, 4, X.PATH_I8_MFMA)
     assert np.array_equal(got, expected(v, N, F))
 
 
