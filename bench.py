@@ -211,6 +211,19 @@ def bench_streaming(dev, n_blocks: int, paced_blocks: int, concurrent_blocks: in
     st = p.stats()
     res["n192_device_unpaced"] = {"blocks": n_blocks, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
                                   "max_ms": st["max_ms"], "rtf": n_blocks * span_s / wall, "dumps": st["dumps"]}
+    # the same stream with 8 blocks per launch (the accumulators are read and
+    # written once per 8 blocks)
+    p.set_fuse(8)
+    p.drain()
+    p.reset_latency()
+    t0 = time.perf_counter()
+    for k in range(n_blocks):
+        p.push(pool[k % pool_n], out=out)
+    p.drain()
+    wall = time.perf_counter() - t0
+    st = p.stats()
+    res["n192_device_unpaced_fuse8"] = {"blocks": n_blocks, "group_p50_ms": st["p50_ms"],
+                                        "group_p99_ms": st["p99_ms"], "rtf": n_blocks * span_s / wall}
     p.close()
 
     # 192 inputs from pinned host memory through the ring, paced at the data rate

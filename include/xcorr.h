@@ -131,6 +131,19 @@ int xcorr_init(const xcorr_config *cfg, void *d_workspace, size_t ws_bytes, xcor
 int xcorr_ingest(xcorr_ctx *ctx, const void *d_volts, int64_t n_samples, uint64_t seq, void *stream);
 
 /*
+ * Correlate n_blocks separate device blocks of block_samples samples each
+ * (d_blocks[b] = [block_samples][F][N]) as consecutive parts of the
+ * integration, with sequence numbers first_seq, first_seq + 1, ...  For
+ * 4+4-bit int8-MFMA contexts with block_samples a multiple of 64, N a
+ * multiple of 16 and 16-byte-aligned blocks, up to 8 blocks go into one
+ * launch (the accumulators are read and written once per launch instead of
+ * once per block); otherwise the blocks are ingested one by one.  Errors as
+ * xcorr_ingest; XCORR_E_INVAL also for n_blocks < 1 or a NULL block.
+ */
+int xcorr_ingest_blocks(xcorr_ctx *ctx, const void *const *d_blocks, int n_blocks, int64_t block_samples,
+                        uint64_t first_seq, void *stream);
+
+/*
  * Write the integration to d_out ([F][P][2], out_bytes from xcorr_query) and
  * start a new one.  A dump of an empty integration writes zeros.
  * n_integrated / n_gaps (may be NULL) receive the samples and the counted
@@ -232,6 +245,13 @@ int xcorr_pipe_push(xcorr_pipe *p, const void *block, int on_host, uint64_t seq,
 int xcorr_pipe_drain(xcorr_pipe *p);
 int xcorr_pipe_stats(const xcorr_pipe *p, xcorr_pipe_stats_t *out);
 int xcorr_pipe_reset_latency(xcorr_pipe *p);
+/* Device blocks: hold up to `fuse` (1..8, default 1) pushed blocks and ingest
+ * them with xcorr_ingest_blocks when the group is full, an integration ends
+ * or the pipe is drained; a latency record then covers the group, from its
+ * ingest's start.  Host blocks are not held.  Held blocks must stay valid
+ * until they are ingested; call xcorr_pipe_drain before xcorr_pipe_destroy
+ * (destroy drops held blocks). */
+int xcorr_pipe_set_fuse(xcorr_pipe *p, int fuse);
 int xcorr_pipe_destroy(xcorr_pipe *p);
 int xcorr_admit(const xcorr_config *cfgs, int n, const int64_t *block_samples, const int32_t *n_slots,
                 size_t budget_bytes, int32_t *admitted, size_t *used_bytes);

@@ -374,11 +374,15 @@ __device__ __forceinline__ void k_step_fused(lds_u8 *const *addr, v16i *acc, int
     });
 }
 
-template <int D, bool TRI, int KC, int NBUF, int VEC, int PROD, int PAR, int HALF>
+// MB = 1: the chunks come from a table of caller blocks (bt), T = all blocks'
+// samples; MB = 0: from one contiguous input (volts).
+template <int D, bool TRI, int KC, int NBUF, int VEC, int PROD, int PAR, int HALF, int MB = 0>
 __device__ __forceinline__ void mfma4f_region(uint8_t *smem, const uint8_t *__restrict__ volts,
                                               int64_t T, int F, int N, int f, int row_blk, int col_blk,
-                                              int2 *__restrict__ acc_out, int accumulate)
+                                              int2 *__restrict__ acc_out, int accumulate,
+                                              const BlockTable *bt = nullptr)
 {
+    static_assert(!MB || (VEC && KC == 64), "block tables feed the LDS-DMA path with 64-row chunks");
     constexpr int NT = n_tiles(D, TRI);
     constexpr int T0 = half_begin(D, TRI, HALF), T1 = half_end(D, TRI, HALF);
     constexpr int NB = TRI ? D : 2 * D;
@@ -427,8 +431,15 @@ __device__ __forceinline__ void mfma4f_region(uint8_t *smem, const uint8_t *__re
     const int nchunks = (int)((T + KC - 1) / KC);
     auto issue = [&](int c, int bufi) {
         const int64_t rows = min((int64_t)KC, T - (int64_t)c * KC);
-        __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
-            (void *)(volts + (int64_t)c * KC * row_bytes), (short)0, (int)(rows * row_bytes), 0x00020000);
+        const uint8_t *base;
+        if constexpr (MB) {
+            const int blk = c / bt->chunks_per_block;
+            base = bt->p[blk] + (int64_t)(c - blk * bt->chunks_per_block) * KC * row_bytes;
+        } else {
+            base = volts + (int64_t)c * KC * row_bytes;
+        }
+        __amdgpu_buffer_rsrc_t rsrc =
+            __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, (int)(rows * row_bytes), 0x00020000);
         lds_u8 *dst = ring + bufi * BUF + wave * LOADS * 1024;
 #pragma unroll
         for (int k = 0; k < LOADS; ++k)
@@ -548,16 +559,17 @@ __device__ __forceinline__ void mfma4f_region(uint8_t *smem, const uint8_t *__re
     }
 }
 
-template <int D, bool TRI, int KC, int NBUF, int VEC>
+template <int D, bool TRI, int KC, int NBUF, int VEC, int MB = 0>
 __device__ __forceinline__ void mfma4f_dispatch(uint8_t *smem, const uint8_t *__restrict__ volts,
                                                 int64_t T, int F, int N, int f, int row_blk, int col_blk,
-                                                int2 *__restrict__ acc_out, int accumulate)
+                                                int2 *__restrict__ acc_out, int accumulate,
+                                                const BlockTable *bt = nullptr)
 {
     switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {
 #define XC_CASE(W)                                                                                     \
     case W:                                                                                            \
-        mfma4f_region<D, TRI, KC, NBUF, VEC, ((W) >> 2), (((W) >> 1) & 1), (((W) & 1) ^ ((W) >> 2))>(  \
-            smem, volts, T, F, N, f, row_blk, col_blk, acc_out, accumulate);                           \
+        mfma4f_region<D, TRI, KC, NBUF, VEC, ((W) >> 2), (((W) >> 1) & 1), (((W) & 1) ^ ((W) >> 2)), MB>( \
+            smem, volts, T, F, N, f, row_blk, col_blk, acc_out, accumulate, bt);                       \
         break;
         XC_CASE(0) XC_CASE(1) XC_CASE(2) XC_CASE(3) XC_CASE(4) XC_CASE(5) XC_CASE(6) XC_CASE(7)
 #undef XC_CASE

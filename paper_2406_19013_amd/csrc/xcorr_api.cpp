@@ -289,6 +289,53 @@ int xcorr_ingest(xcorr_ctx *ctx, const void *d_volts, int64_t n_samples, uint64_
     return XCORR_OK;
 }
 
+int xcorr_ingest_blocks(xcorr_ctx *ctx, const void *const *d_blocks, int n_blocks, int64_t block_samples,
+                        uint64_t first_seq, void *stream)
+{
+    if (!ctx || !d_blocks)
+        return set_error(XCORR_E_INVAL, "ctx or d_blocks is NULL");
+    if (n_blocks < 1 || block_samples < 1)
+        return set_error(XCORR_E_INVAL, "n_blocks and block_samples must be >= 1");
+    for (int b = 0; b < n_blocks; ++b)
+        if (!d_blocks[b])
+            return set_error(XCORR_E_INVAL, "NULL block");
+    if (block_samples > (ctx->max_dump - ctx->acc_samples) / n_blocks)
+        return set_error(XCORR_E_OVERFLOW, "integration would exceed max_samples_per_dump");
+    const xcorr_config &c = ctx->cfg;
+    bool fused = c.sample_bits == 4 && c.path == XCORR_PATH_I8_MFMA && !ctx->per_role && block_samples % 64 == 0 &&
+                 block_samples <= xc::kMaxSamplesPerLaunch4 && c.n_inputs % 16 == 0 &&
+                 64LL * c.n_chans * c.n_inputs < (1LL << 31) - 16;
+    for (int b = 0; b < n_blocks && fused; ++b)
+        fused = (uintptr_t)d_blocks[b] % 16 == 0;
+    if (!fused) {
+        // one ingest per block (other formats and paths, ragged block sizes)
+        for (int b = 0; b < n_blocks; ++b) {
+            const int rc = xcorr_ingest(ctx, d_blocks[b], block_samples, first_seq + b, stream);
+            if (rc)
+                return rc;
+        }
+        return XCORR_OK;
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int group = (int)std::min<int64_t>(xc::kMaxFusedBlocks, xc::kMaxSamplesPerLaunch4 / block_samples);
+    for (int b0 = 0; b0 < n_blocks; b0 += group) {
+        const int n = std::min(group, n_blocks - b0);
+        xc::BlockTable bt{};
+        for (int b = 0; b < n; ++b)
+            bt.p[b] = static_cast<const uint8_t *>(d_blocks[b0 + b]);
+        bt.chunks_per_block = (int)(block_samples / 64);
+        const int accumulate = (ctx->acc_samples > 0 || b0 > 0) ? 1 : 0;
+        const hipError_t e = xc::launch_mfma4f_blocks(ctx->plan, bt, n, c.n_chans, c.n_inputs,
+                                                      static_cast<int2 *>(ctx->ws), accumulate, s);
+        if (e != hipSuccess)
+            return hip_fail(e, "kernel launch");
+        ++ctx->launches;
+    }
+    for (int b = 0; b < n_blocks; ++b)
+        note_ingest(ctx, block_samples, first_seq + b);
+    return XCORR_OK;
+}
+
 int xcorr_dump(xcorr_ctx *ctx, void *d_out, int64_t *n_integrated, uint64_t *n_gaps, void *stream)
 {
     if (!ctx || !d_out)

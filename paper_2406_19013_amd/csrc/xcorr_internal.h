@@ -68,6 +68,17 @@ hipError_t launch_mfma8_d6(const Plan &pl, bool f16, const uint8_t *volts, int64
 
 hipError_t launch_dump(const void *acc, void *out, int64_t bytes, int empty, hipStream_t s);
 
+// Several caller blocks of one array in one 4+4-bit launch: chunk c of the
+// launch is chunk c % chunks_per_block of block c / chunks_per_block (every
+// block holds chunks_per_block whole 64-row chunks).
+constexpr int kMaxFusedBlocks = 8;
+struct BlockTable {
+    const uint8_t *p[kMaxFusedBlocks];
+    int chunks_per_block;
+};
+hipError_t launch_mfma4f_blocks(const Plan &pl, const BlockTable &bt, int n_blocks, int F, int N, int2 *acc,
+                                int accumulate, hipStream_t s);
+
 // Batched persistent launch (4+4-bit, int8 MFMA): one kernel drains a work
 // queue of (array, channel, region) items for up to kMaxBatchArrays arrays of
 // uneven N, F and sample counts.  The descriptors travel by value in the

@@ -49,6 +49,9 @@ struct xcorr_pipe {
     std::vector<float> lat_ms;
     int64_t blocks = 0, dumps = 0, since_dump = 0, host_blocks = 0;
     size_t max_pending = 0;
+    int fuse = 1;                      // device blocks ingested per group
+    std::vector<const void *> held;    // device blocks pushed, not yet ingested
+    uint64_t held_seq0 = 0;
 };
 
 namespace {
@@ -120,6 +123,41 @@ size_t block_bytes_of(const xcorr_ctx *ctx, int64_t block_samples)
 
 size_t round256(size_t x) { return (x + 255) / 256 * 256; }
 
+// Ingest the held device blocks as one group (and dump when asked), under one
+// latency record.
+int flush_held(xcorr_pipe *p, void *d_out, bool dump)
+{
+    if (p->held.empty() && !dump)
+        return XCORR_OK;
+    Record r;
+    int rc = get_record(p, &r);
+    if (rc)
+        return rc;
+    hipError_t e = hipEventRecord(r.begin, p->compute);
+    if (e != hipSuccess) {
+        p->spare.push_back(r);
+        return hip_err(e, "hipEventRecord");
+    }
+    if (!p->held.empty()) {
+        rc = xcorr_ingest_blocks(p->ctx, p->held.data(), (int)p->held.size(), p->block_samples, p->held_seq0,
+                                 p->compute);
+        p->held.clear();
+    }
+    if (rc == XCORR_OK && dump)
+        rc = xcorr_dump(p->ctx, d_out, nullptr, nullptr, p->compute);
+    if (rc) {
+        p->spare.push_back(r);
+        return rc;
+    }
+    e = hipEventRecord(r.end, p->compute);
+    if (e != hipSuccess) {
+        p->spare.push_back(r);
+        return hip_err(e, "hipEventRecord");
+    }
+    p->pending.push_back(r);
+    return XCORR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -186,6 +224,37 @@ int xcorr_pipe_push(xcorr_pipe *p, const void *block, int on_host, uint64_t seq,
     const bool dump_due = p->since_dump + 1 >= p->dump_every;
     if (dump_due && !d_out)
         return api_error(XCORR_E_INVAL, "this block completes an integration: d_out is required");
+    if (!on_host && p->fuse > 1) {
+        // a group holds consecutive sequence numbers
+        if (!p->held.empty() && seq != p->held_seq0 + p->held.size()) {
+            const int rc = flush_held(p, nullptr, false);
+            if (rc)
+                return rc;
+        }
+        if (p->held.empty())
+            p->held_seq0 = seq;
+        p->held.push_back(block);
+        ++p->blocks;
+        ++p->since_dump;
+        int rc = XCORR_OK;
+        if (dump_due) {
+            rc = flush_held(p, d_out, true);
+            if (rc == XCORR_OK) {
+                p->since_dump = 0;
+                ++p->dumps;
+            }
+        } else if ((int)p->held.size() >= p->fuse) {
+            rc = flush_held(p, nullptr, false);
+        }
+        if (dumped)
+            *dumped = rc == XCORR_OK && dump_due;
+        return rc;
+    }
+    if (!p->held.empty()) {   // keep the integration's order
+        const int rc = flush_held(p, nullptr, false);
+        if (rc)
+            return rc;
+    }
     Record r;
     int rc = get_record(p, &r);
     if (rc)
@@ -256,10 +325,24 @@ int xcorr_pipe_push(xcorr_pipe *p, const void *block, int on_host, uint64_t seq,
     return XCORR_OK;
 }
 
+int xcorr_pipe_set_fuse(xcorr_pipe *p, int fuse)
+{
+    if (!p || fuse < 1 || fuse > 8)
+        return api_error(XCORR_E_INVAL, "pipe is NULL or fuse outside 1..8");
+    const int rc = flush_held(p, nullptr, false);
+    if (rc)
+        return rc;
+    p->fuse = fuse;
+    return XCORR_OK;
+}
+
 int xcorr_pipe_drain(xcorr_pipe *p)
 {
     if (!p)
         return api_error(XCORR_E_INVAL, "pipe is NULL");
+    const int rc = flush_held(p, nullptr, false);
+    if (rc)
+        return rc;
     while (!p->pending.empty()) {
         const int rc = reap_one(p);
         if (rc)

@@ -121,6 +121,8 @@ def load(path: str | None = None):
             "xcorr_pipe_drain": [vp],
             "xcorr_pipe_stats": [vp, ctypes.POINTER(PipeStats)],
             "xcorr_pipe_reset_latency": [vp],
+            "xcorr_pipe_set_fuse": [vp, ctypes.c_int],
+            "xcorr_ingest_blocks": [vp, ctypes.POINTER(vp), ctypes.c_int, i64, u64, vp],
             "xcorr_pipe_destroy": [vp],
             "xcorr_admit": [cfgp, ctypes.c_int, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_int32), sz,
                             ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(sz)],
@@ -184,6 +186,13 @@ def xcorr_init(cfg: Config, workspace, ws_bytes: int | None = None) -> ctypes.c_
 def xcorr_ingest(ctx, volts, n_samples: int, seq: int = 0, stream=None):
     _check(load().xcorr_ingest(ctx, ctypes.c_void_p(volts.data_ptr()), int(n_samples), int(seq),
                                _stream_handle(stream)), "xcorr_ingest")
+
+
+def xcorr_ingest_blocks(ctx, blocks, block_samples: int, first_seq: int = 0, stream=None):
+    """blocks: device tensors of block_samples samples each."""
+    arr = (ctypes.c_void_p * len(blocks))(*[b.data_ptr() for b in blocks])
+    _check(load().xcorr_ingest_blocks(ctx, arr, len(blocks), int(block_samples), int(first_seq),
+                                      _stream_handle(stream)), "xcorr_ingest_blocks")
 
 
 def xcorr_dump(ctx, out, stream=None):
@@ -304,6 +313,10 @@ def xcorr_pipe_reset_latency(pipe):
     _check(load().xcorr_pipe_reset_latency(pipe), "xcorr_pipe_reset_latency")
 
 
+def xcorr_pipe_set_fuse(pipe, fuse: int):
+    _check(load().xcorr_pipe_set_fuse(pipe, int(fuse)), "xcorr_pipe_set_fuse")
+
+
 def xcorr_pipe_destroy(pipe):
     _check(load().xcorr_pipe_destroy(pipe), "xcorr_pipe_destroy")
 
@@ -353,6 +366,12 @@ class Correlator:
         s = self._seq if seq is None else seq
         xcorr_ingest(self.ctx, volts, n, s, stream)
         self._seq = s + 1
+
+    def ingest_blocks(self, blocks, seq: int | None = None, stream=None):
+        """Several device blocks of equal length as consecutive samples."""
+        s = self._seq if seq is None else seq
+        xcorr_ingest_blocks(self.ctx, blocks, blocks[0].shape[0], s, stream)
+        self._seq = s + len(blocks)
 
     def dump(self, out=None, stream=None):
         import torch
@@ -451,6 +470,9 @@ class Pipe:
         dumped = xcorr_pipe_push(self.pipe, block, not block.is_cuda, s, out)
         self.seq = s + 1
         return dumped
+
+    def set_fuse(self, fuse: int):
+        xcorr_pipe_set_fuse(self.pipe, fuse)
 
     def drain(self):
         xcorr_pipe_drain(self.pipe)

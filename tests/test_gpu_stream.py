@@ -106,3 +106,54 @@ def test_streaming_workload_first_dump_sampled():
     assert st["dumps"] == 1 and st["blocks"] == every
     p.close()
     c.close()
+
+
+@pytest.mark.parametrize("N,F,B,bits", [(64, 4, 128, 4), (96, 3, 100, 4), (100, 2, 64, 4), (48, 2, 64, 8)],
+                         ids=["one_launch", "ragged_block", "ragged_inputs", "eight_bit"])
+def test_ingest_blocks_matches_oracle(N, F, B, bits):
+    """Five separate device blocks ingested as one integration: one launch
+    when the shape allows it, else one per block; the result is the oracle
+    over the concatenated samples either way."""
+    nb = 5
+    gen = synth.uniform_volts4 if bits == 4 else synth.uniform_volts8
+    blocks = [gen(N, F, B, seed=(4010, N, k)) for k in range(nb)]
+    c = X.Correlator(N, F, bits, X.PATH_I8_MFMA)
+    c.ingest_blocks([b.cuda() for b in blocks])
+    out, n, _ = c.dump()
+    torch.cuda.synchronize()
+    v = torch.cat(blocks)
+    assert n == nb * B
+    assert np.array_equal(out.cpu().numpy(), oracle.to_int32(oracle.xcorr(v.numpy(), bits, nb * B, F, N)))
+    fused = bits == 4 and B % 64 == 0 and N % 16 == 0
+    assert c.stats()["kernel_launches"] == (1 if fused else nb) + 1
+    c.close()
+
+
+def test_pipe_fuses_device_blocks():
+    """fuse = 3, a dump every 7 blocks, 10 blocks: groups of 3, 3 and 1 (the
+    dump), then 3 held until the drain; dumps and the tail match the oracle."""
+    N, F, B, every = 64, 4, 128, 7
+    blocks = [synth.uniform_volts4(N, F, B, seed=(4011, k)) for k in range(10)]
+    c = X.Correlator(N, F, 4, X.PATH_I8_MFMA)
+    p = X.Pipe(c, B, every, host_blocks=False)
+    p.set_fuse(3)
+    out = torch.empty((F, N * (N + 1) // 2, 2), dtype=torch.int32, device="cuda")
+    dev = [b.cuda() for b in blocks]
+    dumped = [p.push(b, out=out) for b in dev]
+    assert dumped == [False] * 6 + [True] + [False] * 3
+    p.drain()
+    torch.cuda.synchronize()
+    first = out.cpu().numpy().copy()
+    v = torch.cat(blocks[:7])
+    assert np.array_equal(first, oracle.to_int32(oracle.xcorr(v.numpy(), 4, 7 * B, F, N)))
+    tail, n, _ = c.dump()
+    torch.cuda.synchronize()
+    v = torch.cat(blocks[7:])
+    assert n == 3 * B
+    assert np.array_equal(tail.cpu().numpy(), oracle.to_int32(oracle.xcorr(v.numpy(), 4, 3 * B, F, N)))
+    st = p.stats()
+    assert st["blocks"] == 10 and st["dumps"] == 1 and st["latencies"] == 4
+    # 4 fused launches (3, 3, 1, 3 blocks) and one dump inside the pipe, one dump above
+    assert c.stats()["kernel_launches"] == 4 + 2
+    p.close()
+    c.close()
