@@ -44,7 +44,7 @@ def measured_traffic(per_launch_algo_bytes: float):
     """HBM bytes per launch of the dominant kernel from the committed
     rocprofv3 FETCH_SIZE / WRITE_SIZE summary, if it was taken on the current
     kernel source; else None."""
-    p = os.path.join(PROFILES, "xc_mfma4_tianlai_traffic.json")
+    p = os.path.join(PROFILES, "xc_mfma4f_tianlai_traffic.json")
     if not os.path.exists(p):
         return None
     try:
@@ -403,7 +403,7 @@ def main():
         "dump_hbm_gbs": dump_gbs,
         "roofline": {"bound": "mfma", "achieved": achieved_tops, "peak": INT8_PEAK_TOPS,
                      "unit": "TFLOP/s", "frac": achieved_tops / INT8_PEAK_TOPS, "traffic": traffic,
-                     "kernel": "xc_mfma4_kernel", "algorithmic_ops_per_launch": algo_ops,
+                     "kernel": "xc_mfma4f_kernel", "algorithmic_ops_per_launch": algo_ops,
                      "hbm_algorithmic_bytes_per_launch": in_bytes + acc_bytes,
                      "hbm_frac": (in_bytes + acc_bytes) / ingest_s / 1e9 / HBM_PEAK_GBS},
     }
