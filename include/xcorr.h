@@ -151,6 +151,17 @@ int xcorr_ingest_blocks(xcorr_ctx *ctx, const void *const *d_blocks, int n_block
  */
 int xcorr_dump(xcorr_ctx *ctx, void *d_out, int64_t *n_integrated, uint64_t *n_gaps, void *stream);
 
+/*
+ * The last ingest of an integration and its dump in one call: as
+ * xcorr_ingest(ctx, d_volts, n_samples, seq) followed by xcorr_dump(ctx,
+ * d_out, ...), with the same results.  On the 4+4-bit int8-MFMA path the
+ * final launch adds the running sums to its own and writes the visibilities
+ * straight into d_out (16-byte aligned), so no separate copy runs; other
+ * paths make the two calls.  Errors as the two calls.
+ */
+int xcorr_ingest_dump(xcorr_ctx *ctx, const void *d_volts, int64_t n_samples, uint64_t seq, void *d_out,
+                      int64_t *n_integrated, uint64_t *n_gaps, void *stream);
+
 int xcorr_stats(const xcorr_ctx *ctx, xcorr_stats_t *out);
 int xcorr_destroy(xcorr_ctx *ctx);
 

@@ -376,10 +376,12 @@ __device__ __forceinline__ void k_step_fused(lds_u8 *const *addr, v16i *acc, int
 
 // MB = 1: the chunks come from a table of caller blocks (bt), T = all blocks'
 // samples; MB = 0: from one contiguous input (volts).
+// accumulate = 1 adds the sums found at acc_in (acc_out for an integration in
+// progress, or the accumulators when the result goes to a separate buffer).
 template <int D, bool TRI, int KC, int NBUF, int VEC, int PROD, int PAR, int HALF, int MB = 0>
 __device__ __forceinline__ void mfma4f_region(uint8_t *smem, const uint8_t *__restrict__ volts,
                                               int64_t T, int F, int N, int f, int row_blk, int col_blk,
-                                              int2 *__restrict__ acc_out, int accumulate,
+                                              int2 *acc_out, const int2 *acc_in, int accumulate,
                                               const BlockTable *bt = nullptr)
 {
     static_assert(!MB || (VEC && KC == 64), "block tables feed the LDS-DMA path with 64-row chunks");
@@ -507,6 +509,7 @@ __device__ __forceinline__ void mfma4f_region(uint8_t *smem, const uint8_t *__re
     }
     const int64_t P = (int64_t)N * (N + 1) / 2;
     int2 *const out_f = acc_out + (int64_t)f * P;
+    const int2 *const in_f = acc_in + (int64_t)f * P;
 #pragma unroll
     for (int t0 = 0; t0 < NT; t0 += G) {
         static_for<T0, T1>([&](auto tc) {
@@ -546,7 +549,7 @@ __device__ __forceinline__ void mfma4f_region(uint8_t *smem, const uint8_t *__re
                     int re = (re0[m] >> 8) + (re1[m] >> 8);
                     int im = ((im0[m] + s0) >> 8) + ((im1[m] + s1) >> 8);
                     if (accumulate) {
-                        const int2 o = out_f[p];
+                        const int2 o = in_f[p];
                         re += o.x;
                         im += o.y;
                     }
@@ -562,14 +565,14 @@ __device__ __forceinline__ void mfma4f_region(uint8_t *smem, const uint8_t *__re
 template <int D, bool TRI, int KC, int NBUF, int VEC, int MB = 0>
 __device__ __forceinline__ void mfma4f_dispatch(uint8_t *smem, const uint8_t *__restrict__ volts,
                                                 int64_t T, int F, int N, int f, int row_blk, int col_blk,
-                                                int2 *__restrict__ acc_out, int accumulate,
+                                                int2 *acc_out, const int2 *acc_in, int accumulate,
                                                 const BlockTable *bt = nullptr)
 {
     switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {
 #define XC_CASE(W)                                                                                     \
     case W:                                                                                            \
         mfma4f_region<D, TRI, KC, NBUF, VEC, ((W) >> 2), (((W) >> 1) & 1), (((W) & 1) ^ ((W) >> 2)), MB>( \
-            smem, volts, T, F, N, f, row_blk, col_blk, acc_out, accumulate, bt);                       \
+            smem, volts, T, F, N, f, row_blk, col_blk, acc_out, acc_in, accumulate, bt);               \
         break;
         XC_CASE(0) XC_CASE(1) XC_CASE(2) XC_CASE(3) XC_CASE(4) XC_CASE(5) XC_CASE(6) XC_CASE(7)
 #undef XC_CASE

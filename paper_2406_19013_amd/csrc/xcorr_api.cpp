@@ -289,6 +289,52 @@ int xcorr_ingest(xcorr_ctx *ctx, const void *d_volts, int64_t n_samples, uint64_
     return XCORR_OK;
 }
 
+int xcorr_ingest_dump(xcorr_ctx *ctx, const void *d_volts, int64_t n_samples, uint64_t seq, void *d_out,
+                      int64_t *n_integrated, uint64_t *n_gaps, void *stream)
+{
+    if (!ctx || !d_volts || !d_out)
+        return set_error(XCORR_E_INVAL, "ctx, d_volts or d_out is NULL");
+    if (n_samples < 1)
+        return set_error(XCORR_E_INVAL, "n_samples must be >= 1");
+    if (n_samples > ctx->max_dump - ctx->acc_samples)
+        return set_error(XCORR_E_OVERFLOW, "integration would exceed max_samples_per_dump");
+    if ((uintptr_t)d_out % 16)
+        return set_error(XCORR_E_INVAL, "d_out must be 16-byte aligned");
+    const xcorr_config &c = ctx->cfg;
+    if (!(c.sample_bits == 4 && c.path == XCORR_PATH_I8_MFMA && !ctx->per_role)) {
+        const int rc = xcorr_ingest(ctx, d_volts, n_samples, seq, stream);
+        return rc ? rc : xcorr_dump(ctx, d_out, n_integrated, n_gaps, stream);
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const uint8_t *v = static_cast<const uint8_t *>(d_volts);
+    int2 *acc = static_cast<int2 *>(ctx->ws);
+    const int64_t bytes_per_row = (int64_t)c.n_chans * c.n_inputs;
+    const int64_t L = xc::kMaxSamplesPerLaunch4;
+    for (int64_t t0 = 0; t0 < n_samples; t0 += L) {
+        const int64_t tl = std::min<int64_t>(L, n_samples - t0);
+        const int accumulate = (ctx->acc_samples > 0 || t0 > 0) ? 1 : 0;
+        const bool last = t0 + tl >= n_samples;
+        // the last launch adds the running sums to its own and writes the
+        // result to d_out: the integration ends without a copy
+        const hipError_t e = last ? xc::launch_mfma4f(ctx->plan, v + t0 * bytes_per_row, tl, c.n_chans,
+                                                      c.n_inputs, static_cast<int2 *>(d_out), accumulate, s, acc)
+                                  : xc::launch_mfma4f(ctx->plan, v + t0 * bytes_per_row, tl, c.n_chans,
+                                                      c.n_inputs, acc, accumulate, s);
+        if (e != hipSuccess)
+            return hip_fail(e, "kernel launch");
+        ++ctx->launches;
+    }
+    note_ingest(ctx, n_samples, seq);
+    if (n_integrated)
+        *n_integrated = ctx->acc_samples;
+    if (n_gaps)
+        *n_gaps = ctx->gaps;
+    ctx->acc_samples = 0;
+    ctx->gaps = 0;
+    ++ctx->dumps;
+    return XCORR_OK;
+}
+
 int xcorr_ingest_blocks(xcorr_ctx *ctx, const void *const *d_blocks, int n_blocks, int64_t block_samples,
                         uint64_t first_seq, void *stream)
 {

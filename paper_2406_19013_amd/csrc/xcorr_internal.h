@@ -46,8 +46,10 @@ hipError_t launch_plain(int bits, const uint8_t *volts, int64_t T, int F, int N,
 hipError_t launch_mfma4(const Plan &pl, int kc, const uint8_t *volts, int64_t T, int F, int N,
                         int2 *acc, int accumulate, hipStream_t s);
 // fused-product variant (one Re and one Im accumulator per tile), the default
+// acc_in (default: acc) is where accumulate = 1 reads the running sums; with
+// acc_in != acc the result goes to acc (e.g. a caller's dump buffer).
 hipError_t launch_mfma4f(const Plan &pl, const uint8_t *volts, int64_t T, int F, int N, int2 *acc,
-                         int accumulate, hipStream_t s);
+                         int accumulate, hipStream_t s, const int2 *acc_in = nullptr);
 // 8+8-bit input, int8 MFMA (f16 = false, int2 accumulators) or FP16 MFMA with
 // FP32 accumulation (f16 = true, float2 accumulators).
 hipError_t launch_mfma8(const Plan &pl, bool f16, const uint8_t *volts, int64_t T, int F, int N, void *acc,
@@ -77,7 +79,7 @@ struct BlockTable {
     int chunks_per_block;
 };
 hipError_t launch_mfma4f_blocks(const Plan &pl, const BlockTable &bt, int n_blocks, int F, int N, int2 *acc,
-                                int accumulate, hipStream_t s);
+                                int accumulate, hipStream_t s, const int2 *acc_in = nullptr);
 
 // Batched persistent launch (4+4-bit, int8 MFMA): one kernel drains a work
 // queue of (array, channel, region) items for up to kMaxBatchArrays arrays of

@@ -123,6 +123,7 @@ def load(path: str | None = None):
             "xcorr_pipe_reset_latency": [vp],
             "xcorr_pipe_set_fuse": [vp, ctypes.c_int],
             "xcorr_ingest_blocks": [vp, ctypes.POINTER(vp), ctypes.c_int, i64, u64, vp],
+            "xcorr_ingest_dump": [vp, vp, i64, u64, vp, ctypes.POINTER(i64), ctypes.POINTER(u64), vp],
             "xcorr_pipe_destroy": [vp],
             "xcorr_admit": [cfgp, ctypes.c_int, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_int32), sz,
                             ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(sz)],
@@ -193,6 +194,15 @@ def xcorr_ingest_blocks(ctx, blocks, block_samples: int, first_seq: int = 0, str
     arr = (ctypes.c_void_p * len(blocks))(*[b.data_ptr() for b in blocks])
     _check(load().xcorr_ingest_blocks(ctx, arr, len(blocks), int(block_samples), int(first_seq),
                                       _stream_handle(stream)), "xcorr_ingest_blocks")
+
+
+def xcorr_ingest_dump(ctx, volts, n_samples: int, seq: int, out, stream=None):
+    """Last ingest of an integration plus its dump; returns (n_integrated, n_gaps)."""
+    n, g = ctypes.c_int64(), ctypes.c_uint64()
+    _check(load().xcorr_ingest_dump(ctx, ctypes.c_void_p(volts.data_ptr()), int(n_samples), int(seq),
+                                    ctypes.c_void_p(out.data_ptr()), ctypes.byref(n), ctypes.byref(g),
+                                    _stream_handle(stream)), "xcorr_ingest_dump")
+    return n.value, g.value
 
 
 def xcorr_dump(ctx, out, stream=None):
@@ -366,6 +376,18 @@ class Correlator:
         s = self._seq if seq is None else seq
         xcorr_ingest(self.ctx, volts, n, s, stream)
         self._seq = s + 1
+
+    def ingest_dump(self, volts, out=None, n_samples: int | None = None, seq: int | None = None, stream=None):
+        """Ingest the last block of an integration and dump it: (out, n, gaps)."""
+        import torch
+        if out is None:
+            dt = torch.float32 if self.path == PATH_F16_MFMA else torch.int32
+            out = torch.empty((self.n_chans, self.n_pairs, 2), dtype=dt, device=self.device)
+        n = volts.shape[0] if n_samples is None else n_samples
+        s = self._seq if seq is None else seq
+        n_int, gaps = xcorr_ingest_dump(self.ctx, volts, n, s, out, stream)
+        self._seq = s + 1
+        return out, n_int, gaps
 
     def ingest_blocks(self, blocks, seq: int | None = None, stream=None):
         """Several device blocks of equal length as consecutive samples."""

@@ -233,3 +233,44 @@ def test_persistent_workgroups_walk_many_regions(N, F, tile):
     chans = sorted(set([0, 1, F // 3, F // 2, F - 2, F - 1]))
     ref = oracle.to_int32(oracle.xcorr(v.numpy(), 4, T, F, N, chans=chans))
     assert np.array_equal(got[chans], ref)
+
+
+@pytest.mark.parametrize("N,F,splits", [(192, 4, [300]), (64, 3, [100, 129]), (100, 2, [64, 77]),
+                                         (16, 1, [140_001])],
+                         ids=["one_ingest", "after_ingest", "ragged_inputs", "launch_split"])
+def test_ingest_dump_writes_the_integration(N, F, splits):
+    """The last ingest fused with its dump: the output equals the oracle over
+    every sample of the integration, and the integration is empty after it."""
+    T = sum(splits)
+    _say(f"ingest_dump N={N} F={F} splits={splits}")
+    v = synth.uniform_volts4(N, F, T, seed=(1010, N, T))
+    vd = v.cuda()
+    c = X.Correlator(N, F, 4, X.PATH_I8_MFMA)
+    t0 = 0
+    for n in splits[:-1]:
+        c.ingest(vd[t0:t0 + n], n)
+        t0 += n
+    out, n_int, gaps = c.ingest_dump(vd[t0:], n_samples=splits[-1])
+    torch.cuda.synchronize()
+    assert n_int == T and gaps == 0
+    assert np.array_equal(out.cpu().numpy(), expected(v, N, F))
+    assert c.stats()["samples_integrated"] == 0 and c.stats()["dumps"] == 1
+    empty, n0, _ = c.dump()
+    torch.cuda.synchronize()
+    assert n0 == 0 and not empty.cpu().numpy().any()
+    # the next integration starts from zero
+    out2, n2, _ = c.ingest_dump(vd[:50], n_samples=50)
+    torch.cuda.synchronize()
+    assert n2 == 50 and np.array_equal(out2.cpu().numpy(), expected(v[:50], N, F))
+    c.close()
+
+
+def test_ingest_dump_on_other_paths_matches_two_calls():
+    N, F, T = 40, 2, 90
+    v = synth.uniform_volts8(N, F, T, seed=(1011,))
+    for path in (X.PATH_I8_MFMA, X.PATH_PLAIN):
+        c = X.Correlator(N, F, 8, path)
+        out, n, _ = c.ingest_dump(v.cuda(), n_samples=T)
+        torch.cuda.synchronize()
+        assert n == T and np.array_equal(out.cpu().numpy(), oracle.to_int32(oracle.xcorr(v.numpy(), 8, T, F, N)))
+        c.close()
