@@ -85,6 +85,11 @@ __device__ __forceinline__ void wait_vmcnt()
 
 constexpr int kBufferOutOfRange = (int)0xFFFFFFF0;  // any offset >= num_records reads 0
 
+// Cache policy of the LDS-DMA input loads (sc0 | nt | sc1): every input byte
+// is read exactly once per launch, as a stream.  Measured 9 % faster on the
+// 192-input kernel than the default policy, with identical results.
+constexpr int kStreamLoadPolicy = 1 | 2 | 16;
+
 // Work-group barrier without the release/acquire fence of __syncthreads (the
 // fence would wait for every LDS-DMA load in flight, i.e. drain the ring).
 // The "memory" clobber keeps the compiler from moving LDS accesses across it;

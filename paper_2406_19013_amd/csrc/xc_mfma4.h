@@ -161,7 +161,7 @@ __device__ __forceinline__ void mfma4_region(uint8_t *smem, const uint8_t *__res
 #pragma unroll
         for (int k = 0; k < LOADS; ++k)
             __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (__attribute__((address_space(3))) void *)(dst + k * 1024),
-                                                     16, voff[k], 0, 0, 0);
+                                                     16, voff[k], 0, 0, kStreamLoadPolicy);
     };
     auto fill_sync = [&](int c, int bufi) {
         lds_u8 *dst = ring + bufi * BUF;
@@ -446,7 +446,7 @@ __device__ __forceinline__ void mfma4f_region(uint8_t *smem, const uint8_t *__re
 #pragma unroll
         for (int k = 0; k < LOADS; ++k)
             __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (__attribute__((address_space(3))) void *)(dst + k * 1024),
-                                                     16, voff[k], 0, 0, 0);
+                                                     16, voff[k], 0, 0, kStreamLoadPolicy);
     };
     auto fill_sync = [&](int c, int bufi) {
         lds_u8 *dst = ring + bufi * BUF;
