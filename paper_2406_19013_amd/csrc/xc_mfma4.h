@@ -378,7 +378,9 @@ __device__ __forceinline__ void k_step_fused(lds_u8 *const *addr, v16i *acc, int
 // samples; MB = 0: from one contiguous input (volts).
 // accumulate = 1 adds the sums found at acc_in (acc_out for an integration in
 // progress, or the accumulators when the result goes to a separate buffer).
-template <int D, bool TRI, int KC, int NBUF, int VEC, int PROD, int PAR, int HALF, int MB = 0>
+// ACC: 0 = the launch overwrites, 1 = it accumulates (the running sums are
+// loaded in batches), 2 = the `accumulate` argument decides (per element).
+template <int D, bool TRI, int KC, int NBUF, int VEC, int PROD, int PAR, int HALF, int MB = 0, int ACC = 2>
 __device__ __forceinline__ void mfma4f_region(uint8_t *smem, const uint8_t *__restrict__ volts,
                                               int64_t T, int F, int N, int f, int row_blk, int col_blk,
                                               int2 *acc_out, const int2 *acc_in, int accumulate,
@@ -524,8 +526,10 @@ __device__ __forceinline__ void mfma4f_region(uint8_t *smem, const uint8_t *__re
             }
         });
         __syncthreads();
-        const int NQ = (NT - t0 < G ? NT - t0 : G) * 256;
-        for (int qq = tid; qq < NQ; qq += kMfmaThreads) {
+        const int NQ = (NT - t0 < G ? NT - t0 : G) * 256;   // (tile, rq, lane) quads this round
+        // emit one quad: rows i0..i0+3 of column j; `old` supplies the running
+        // sums when accumulating
+        auto emit = [&](int qq, auto &&old) {
             const int u = qq >> 8, rq = (qq >> 6) & 3, ln = qq & 63;
             const int t = t0 + u;
             const int I = TRI ? tri_I_rt(t) : t / D;
@@ -548,21 +552,55 @@ __device__ __forceinline__ void mfma4f_region(uint8_t *smem, const uint8_t *__re
                     const int s1 = sstage[(D + I) * 64 + il] + sstage[(D + I) * 64 + 32 + il];
                     int re = (re0[m] >> 8) + (re1[m] >> 8);
                     int im = ((im0[m] + s0) >> 8) + ((im1[m] + s1) >> 8);
-                    if (accumulate) {
-                        const int2 o = in_f[p];
-                        re += o.x;
-                        im += o.y;
-                    }
-                    out_f[p] = make_int2(re, im);
+                    const int2 o = old(m, p);
+                    out_f[p] = make_int2(re + o.x, im + o.y);
                 }
                 p += i + 1;
+            }
+        };
+        if constexpr (ACC == 0) {
+            for (int qq = tid; qq < NQ; qq += kMfmaThreads)
+                emit(qq, [](int, int64_t) { return make_int2(0, 0); });
+        } else if constexpr (ACC == 2 || D <= 3) {
+            // per element (D <= 3 has no registers to spare for the batch below)
+            for (int qq = tid; qq < NQ; qq += kMfmaThreads)
+                emit(qq, [&](int, int64_t p) { return accumulate ? in_f[p] : make_int2(0, 0); });
+        } else {
+            // the running sums of all this thread's quads are loaded first
+            // (from a valid address even where the pair is not stored), so
+            // that their latencies overlap instead of one load per element
+            constexpr int QPT = (G * 256 + kMfmaThreads - 1) / kMfmaThreads;
+            int2 old[QPT][4];
+#pragma unroll
+            for (int k = 0; k < QPT; ++k) {
+                const int qq = tid + k * kMfmaThreads;
+                const int u = qq >> 8, rq = (qq >> 6) & 3, ln = qq & 63;
+                const int t = t0 + u;
+                const int I = TRI ? tri_I_rt(t) : t / D;
+                const int J = TRI ? tri_J_rt(t) : t % D;
+                const int i0 = (row_blk + I) * 32 + 8 * rq + 4 * (ln >> 5);
+                const int j = (col_blk + J) * 32 + (ln & 31);
+                int64_t p = (int64_t)i0 * (i0 + 1) / 2 + j;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const int i = i0 + m;
+                    const bool ok = qq < NQ && i < N && j <= i;
+                    old[k][m] = in_f[ok ? p : 0];
+                    p += i + 1;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < QPT; ++k) {
+                const int qq = tid + k * kMfmaThreads;
+                if (qq < NQ)
+                    emit(qq, [&](int m, int64_t) { return old[k][m]; });
             }
         }
         __syncthreads();
     }
 }
 
-template <int D, bool TRI, int KC, int NBUF, int VEC, int MB = 0>
+template <int D, bool TRI, int KC, int NBUF, int VEC, int MB = 0, int ACC = 2>
 __device__ __forceinline__ void mfma4f_dispatch(uint8_t *smem, const uint8_t *__restrict__ volts,
                                                 int64_t T, int F, int N, int f, int row_blk, int col_blk,
                                                 int2 *acc_out, const int2 *acc_in, int accumulate,
@@ -571,7 +609,7 @@ __device__ __forceinline__ void mfma4f_dispatch(uint8_t *smem, const uint8_t *__
     switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {
 #define XC_CASE(W)                                                                                     \
     case W:                                                                                            \
-        mfma4f_region<D, TRI, KC, NBUF, VEC, ((W) >> 2), (((W) >> 1) & 1), (((W) & 1) ^ ((W) >> 2)), MB>( \
+        mfma4f_region<D, TRI, KC, NBUF, VEC, ((W) >> 2), (((W) >> 1) & 1), (((W) & 1) ^ ((W) >> 2)), MB, ACC>( \
             smem, volts, T, F, N, f, row_blk, col_blk, acc_out, acc_in, accumulate, bt);               \
         break;
         XC_CASE(0) XC_CASE(1) XC_CASE(2) XC_CASE(3) XC_CASE(4) XC_CASE(5) XC_CASE(6) XC_CASE(7)

@@ -12,7 +12,7 @@ namespace {
 // 256 registers), one above.
 constexpr int fused_wgs_per_cu(int D) { return D <= 3 ? 2 : 1; }
 
-template <int D, int VEC>
+template <int D, int VEC, int ACC>
 __global__ __launch_bounds__(kMfmaThreads)
 __attribute__((amdgpu_waves_per_eu(2 * fused_wgs_per_cu(D), 2 * fused_wgs_per_cu(D))))
 void xc_mfma4f_kernel(const uint8_t *__restrict__ volts, int64_t T, int F, int N, int nseg, int R,
@@ -28,8 +28,8 @@ void xc_mfma4f_kernel(const uint8_t *__restrict__ volts, int64_t T, int F, int N
     const int f = item / R;
     const int r = item - f * R;
     if (r < nseg) {
-        mfma4f_dispatch<D, true, KC, NBUF, VEC>(smem, volts, T, F, N, f, r * D, r * D, acc_out, acc_in,
-                                                accumulate);
+        mfma4f_dispatch<D, true, KC, NBUF, VEC, 0, ACC>(smem, volts, T, F, N, f, r * D, r * D, acc_out, acc_in,
+                                                        accumulate);
     } else if constexpr (D <= 4) {
         const int k = r - nseg;
         int a = (int)((1.f + sqrtf(1.f + 8.f * k)) * 0.5f);
@@ -38,14 +38,14 @@ void xc_mfma4f_kernel(const uint8_t *__restrict__ volts, int64_t T, int F, int N
         while ((a + 1) * a / 2 <= k)
             ++a;
         const int b = k - a * (a - 1) / 2;
-        mfma4f_dispatch<D, false, KC, NBUF, VEC>(smem, volts, T, F, N, f, a * D, b * D, acc_out, acc_in,
-                                                 accumulate);
+        mfma4f_dispatch<D, false, KC, NBUF, VEC, 0, ACC>(smem, volts, T, F, N, f, a * D, b * D, acc_out,
+                                                         acc_in, accumulate);
     }
 }
 
 // Several blocks of one array in one launch (16-byte-aligned blocks, N a
 // multiple of 16): as above, with the chunks taken from the block table.
-template <int D>
+template <int D, int ACC>
 __global__ __launch_bounds__(kMfmaThreads)
 __attribute__((amdgpu_waves_per_eu(2 * fused_wgs_per_cu(D), 2 * fused_wgs_per_cu(D))))
 void xc_mfma4f_blocks_kernel(const BlockTable bt, int64_t T, int F, int N, int nseg, int R, int nitems,
@@ -61,8 +61,8 @@ void xc_mfma4f_blocks_kernel(const BlockTable bt, int64_t T, int F, int N, int n
     const int f = item / R;
     const int r = item - f * R;
     if (r < nseg) {
-        mfma4f_dispatch<D, true, KC, NBUF, 1, 1>(smem, nullptr, T, F, N, f, r * D, r * D, acc_out, acc_in,
-                                                 accumulate, &bt);
+        mfma4f_dispatch<D, true, KC, NBUF, 1, 1, ACC>(smem, nullptr, T, F, N, f, r * D, r * D, acc_out, acc_in,
+                                                      accumulate, &bt);
     } else if constexpr (D <= 4) {
         const int k = r - nseg;
         int a = (int)((1.f + sqrtf(1.f + 8.f * k)) * 0.5f);
@@ -71,8 +71,8 @@ void xc_mfma4f_blocks_kernel(const BlockTable bt, int64_t T, int F, int N, int n
         while ((a + 1) * a / 2 <= k)
             ++a;
         const int b = k - a * (a - 1) / 2;
-        mfma4f_dispatch<D, false, KC, NBUF, 1, 1>(smem, nullptr, T, F, N, f, a * D, b * D, acc_out, acc_in,
-                                                  accumulate, &bt);
+        mfma4f_dispatch<D, false, KC, NBUF, 1, 1, ACC>(smem, nullptr, T, F, N, f, a * D, b * D, acc_out,
+                                                       acc_in, accumulate, &bt);
     }
 }
 
@@ -87,8 +87,9 @@ static hipError_t launch_mfma4f_blocks_t(const Plan &pl, const BlockTable &bt, i
         return hipErrorInvalidValue;
     const int nitems = (int)nitems64;
     const int64_t T = (int64_t)n_blocks * bt.chunks_per_block * 64;
-    hipLaunchKernelGGL(xc_mfma4f_blocks_kernel<D>, dim3(xcd_grid(nitems)), dim3(kMfmaThreads), 0, s, bt, T, F,
-                       N, pl.nseg, pl.regions, nitems, acc, acc_in ? acc_in : acc, accumulate);
+    auto kern = accumulate ? xc_mfma4f_blocks_kernel<D, 1> : xc_mfma4f_blocks_kernel<D, 0>;
+    hipLaunchKernelGGL(kern, dim3(xcd_grid(nitems)), dim3(kMfmaThreads), 0, s, bt, T, F, N, pl.nseg, pl.regions,
+                       nitems, acc, acc_in ? acc_in : acc, accumulate);
     return hipGetLastError();
 }
 
@@ -123,7 +124,10 @@ static hipError_t launch_mfma4f_t(const Plan &pl, const uint8_t *volts, int64_t 
     const int nitems = (int)nitems64;
     const int vec_ok = (N % 16 == 0) && ((uintptr_t)volts % 16 == 0) &&
                        64LL * F * N < (1LL << 31) - 16;
-    auto kern = vec_ok ? xc_mfma4f_kernel<D, 1> : xc_mfma4f_kernel<D, 0>;
+    // overwrite and accumulate are separate kernels: the batched loads of the
+    // accumulating epilogue cost the overwriting one registers and time
+    auto kern = vec_ok ? (accumulate ? xc_mfma4f_kernel<D, 1, 1> : xc_mfma4f_kernel<D, 1, 0>)
+                       : (accumulate ? xc_mfma4f_kernel<D, 0, 1> : xc_mfma4f_kernel<D, 0, 0>);
     hipLaunchKernelGGL(kern, dim3(xcd_grid(nitems)), dim3(kMfmaThreads), 0, s, volts, T, F, N,
                        pl.nseg, pl.regions, nitems, acc, acc_in ? acc_in : acc, accumulate);
     return hipGetLastError();
