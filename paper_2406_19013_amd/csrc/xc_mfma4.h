@@ -310,8 +310,10 @@ __device__ __forceinline__ void mfma4_dispatch(uint8_t *smem, const uint8_t *__r
 // int32 sum exceeds the bound: per parity |partial| <= 32896 per sample.
 
 constexpr int fused_role(int prod, int par) { return prod + 2 * par; }
-// tiles per epilogue round: 4 roles x G x 4 KB plus the row sums fit the ring
-constexpr int fused_epilogue_tiles(int D) { return D <= 3 ? 3 : 6; }
+// tiles per epilogue round: the stage (4 roles x G x 4 KB plus the row sums)
+// fits the ring for D <= 3 (two work-groups per CU); for D >= 4 it takes
+// 131 KB, more than the ring, so that D = 6's 21 tiles need three rounds
+constexpr int fused_epilogue_tiles(int D) { return D <= 3 ? 3 : 8; }
 // ring depth (64-row chunks of 16 KB): as deep as LDS allows, one work-group
 // per CU for D >= 4, two for D <= 3
 constexpr int fused_nbuf(int D) { return D <= 3 ? 4 : 8; }
@@ -320,6 +322,36 @@ constexpr int fused_smem_bytes(int D)
     return fused_nbuf(D) * 64 * kRowBytes > fused_epilogue_tiles(D) * 16384 + 2 * D * 256
                ? fused_nbuf(D) * 64 * kRowBytes
                : fused_epilogue_tiles(D) * 16384 + 2 * D * 256;
+}
+
+// Epilogue rounds: slot u of round rc holds tile fused_slot_tile(...), or -1.
+// With an even G each round takes G/2 tiles from each half, so that every
+// wave frees registers from the first round on; with an odd G tiles go in
+// order.
+constexpr int fused_slot_tile(int D, bool tri, int rc, int u)
+{
+    const int G = fused_epilogue_tiles(D), NT = n_tiles(D, tri);
+    if (G % 2) {
+        const int t = rc * G + u;
+        return t < NT ? t : -1;
+    }
+    const int H = G / 2, h = u < H ? 0 : 1;
+    const int t = half_begin(D, tri, h) + rc * H + (u - h * H);
+    return t < half_end(D, tri, h) ? t : -1;
+}
+constexpr int fused_rounds(int D, bool tri)
+{
+    int r = 0;
+    for (int t = 0; t < n_tiles(D, tri); ++t) {
+        bool found = false;
+        for (int rc = 0; !found; ++rc)
+            for (int u = 0; u < fused_epilogue_tiles(D); ++u)
+                if (fused_slot_tile(D, tri, rc, u) == t) {
+                    found = true;
+                    r = rc + 1 > r ? rc + 1 : r;
+                }
+    }
+    return r;
 }
 
 // Does half HALF compute the row sums of row block I (the half owning the
@@ -498,106 +530,114 @@ __device__ __forceinline__ void mfma4f_region(uint8_t *smem, const uint8_t *__re
     }
     __syncthreads();
 
-    // Epilogue: stage [role = (product, parity)][tile][rq][lane] v4i, then the
-    // row sums [parity][row block][64 lanes]; emit descales each parity.
+    // Epilogue, in rounds of G tiles: stage [role = (product, parity)][slot]
+    // [rq][lane] v4i and the row sums [parity][row block][64 lanes]; then each
+    // thread adds the four roles of its quads (rows i0..i0+3 of one column),
+    // descales each parity separately and stores.  A wave's quads are known at
+    // compile time: slots u = PROD, PROD + 2, ... of the round, row quad
+    // rq = 2 PAR + (HALF ^ PROD), which is the wave's index mod 4.
     typedef __attribute__((address_space(3))) v4i lds_v4i;
     lds_v4i *const stage = (lds_v4i *)smem;
     int *const sstage = (int *)(smem + 4 * G * 4096);
+    // lane offsets of the epilogue, from an opaque copy of the thread index so
+    // that none of them is computed before the K loop and held across it
+    int etid = threadIdx.x;
+    asm volatile("" : "+v"(etid));
+    const int elane = etid & 63;
     if constexpr (PROD == 1) {
         static_for<0, D>([&](auto bc) {
             if constexpr (owns_rowsum(D, TRI, HALF, bc))
-                sstage[(PAR * D + bc) * 64 + lane] = rsum[bc];
+                sstage[(PAR * D + bc) * 64 + elane] = rsum[bc];
         });
     }
+    constexpr int RQ = 2 * PAR + (HALF ^ PROD);
+    constexpr int KQ = (G + 1) / 2;
     const int64_t P = (int64_t)N * (N + 1) / 2;
     int2 *const out_f = acc_out + (int64_t)f * P;
     const int2 *const in_f = acc_in + (int64_t)f * P;
-#pragma unroll
-    for (int t0 = 0; t0 < NT; t0 += G) {
-        static_for<T0, T1>([&](auto tc) {
-            constexpr int t = tc;
-            const int u = t - t0;
-            if (u >= 0 && u < G) {
-#pragma unroll
-                for (int rq = 0; rq < 4; ++rq)
-                    stage[((ROLE * G + u) * 4 + rq) * 64 + lane] =
+    const int il0 = 8 * RQ + 4 * (elane >> 5);   // first row of the quad within its 32-row block
+    const int jl = elane & 31;
+    static_for<0, fused_rounds(D, TRI)>([&](auto rc) {
+        static_for<0, G>([&](auto uc) {
+            constexpr int u = uc;
+            constexpr int t = fused_slot_tile(D, TRI, rc, u);
+            if constexpr (t >= T0 && t < T1) {
+                static_for<0, 4>([&](auto rqc) {
+                    constexpr int rq = rqc;
+                    stage[((ROLE * G + u) * 4 + rq) * 64 + elane] =
                         v4i{acc[t - T0][4 * rq], acc[t - T0][4 * rq + 1], acc[t - T0][4 * rq + 2],
                             acc[t - T0][4 * rq + 3]};
+                });
             }
         });
         __syncthreads();
-        const int NQ = (NT - t0 < G ? NT - t0 : G) * 256;   // (tile, rq, lane) quads this round
-        // emit one quad: rows i0..i0+3 of column j; `old` supplies the running
-        // sums when accumulating
-        auto emit = [&](int qq, auto &&old) {
-            const int u = qq >> 8, rq = (qq >> 6) & 3, ln = qq & 63;
-            const int t = t0 + u;
-            const int I = TRI ? tri_I_rt(t) : t / D;
-            const int J = TRI ? tri_J_rt(t) : t % D;
-            const int i0 = (row_blk + I) * 32 + 8 * rq + 4 * (ln >> 5);
-            const int j = (col_blk + J) * 32 + (ln & 31);
-            const int e = (u * 4 + rq) * 64 + ln;
-            const v4i re0 = stage[(fused_role(0, 0) * G * 4) * 64 + e];
-            const v4i re1 = stage[(fused_role(0, 1) * G * 4) * 64 + e];
-            const v4i im0 = stage[(fused_role(1, 0) * G * 4) * 64 + e];
-            const v4i im1 = stage[(fused_role(1, 1) * G * 4) * 64 + e];
-            const int il0 = 8 * rq + 4 * (ln >> 5);
-            int64_t p = (int64_t)i0 * (i0 + 1) / 2 + j;
+        // running sums of every quad of this thread, loaded before any store
+        // (from a valid address where the pair does not exist)
+        int2 old[ACC == 1 && D > 3 ? KQ : 1][4];
+        if constexpr (ACC == 1 && D > 3) {
+            static_for<0, KQ>([&](auto kc) {
+                constexpr int u = PROD + 2 * kc;
+                constexpr int t = u < G ? fused_slot_tile(D, TRI, rc, u) : -1;
+                if constexpr (t >= 0) {
+                    constexpr int I = tile_I(D, TRI, t), J = tile_J(D, TRI, t);
+                    const int i0 = (row_blk + I) * 32 + il0;
+                    const int j = (col_blk + J) * 32 + jl;
+                    int p = i0 * (i0 + 1) / 2 + j;
 #pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const int i = i0 + m;
-                if (i < N && j <= i) {
-                    const int il = il0 + m;
-                    const int s0 = sstage[I * 64 + il] + sstage[I * 64 + 32 + il];
-                    const int s1 = sstage[(D + I) * 64 + il] + sstage[(D + I) * 64 + 32 + il];
-                    int re = (re0[m] >> 8) + (re1[m] >> 8);
-                    int im = ((im0[m] + s0) >> 8) + ((im1[m] + s1) >> 8);
-                    const int2 o = old(m, p);
-                    out_f[p] = make_int2(re + o.x, im + o.y);
+                    for (int m = 0; m < 4; ++m) {
+                        const int i = i0 + m;
+                        const bool ok = i < N && (!(TRI && I == J) || j <= i);
+                        old[kc][m] = in_f[ok ? p : 0];
+                        p += i + 1;
+                    }
                 }
-                p += i + 1;
-            }
-        };
-        if constexpr (ACC == 0) {
-            for (int qq = tid; qq < NQ; qq += kMfmaThreads)
-                emit(qq, [](int, int64_t) { return make_int2(0, 0); });
-        } else if constexpr (ACC == 2 || D <= 3) {
-            // per element (D <= 3 has no registers to spare for the batch below)
-            for (int qq = tid; qq < NQ; qq += kMfmaThreads)
-                emit(qq, [&](int, int64_t p) { return accumulate ? in_f[p] : make_int2(0, 0); });
-        } else {
-            // the running sums of all this thread's quads are loaded first
-            // (from a valid address even where the pair is not stored), so
-            // that their latencies overlap instead of one load per element
-            constexpr int QPT = (G * 256 + kMfmaThreads - 1) / kMfmaThreads;
-            int2 old[QPT][4];
-#pragma unroll
-            for (int k = 0; k < QPT; ++k) {
-                const int qq = tid + k * kMfmaThreads;
-                const int u = qq >> 8, rq = (qq >> 6) & 3, ln = qq & 63;
-                const int t = t0 + u;
-                const int I = TRI ? tri_I_rt(t) : t / D;
-                const int J = TRI ? tri_J_rt(t) : t % D;
-                const int i0 = (row_blk + I) * 32 + 8 * rq + 4 * (ln >> 5);
-                const int j = (col_blk + J) * 32 + (ln & 31);
-                int64_t p = (int64_t)i0 * (i0 + 1) / 2 + j;
+            });
+        }
+        static_for<0, KQ>([&](auto kc) {
+            constexpr int u = PROD + 2 * kc;
+            constexpr int t = u < G ? fused_slot_tile(D, TRI, rc, u) : -1;
+            if constexpr (t >= 0) {
+                constexpr int I = tile_I(D, TRI, t), J = tile_J(D, TRI, t);
+                constexpr bool diag = TRI && I == J;
+                const int i0 = (row_blk + I) * 32 + il0;
+                const int j = (col_blk + J) * 32 + jl;
+                const int e = (u * 4 + RQ) * 64 + elane;
+                const v4i re0 = stage[(fused_role(0, 0) * G * 4) * 64 + e];
+                const v4i re1 = stage[(fused_role(0, 1) * G * 4) * 64 + e];
+                const v4i im0 = stage[(fused_role(1, 0) * G * 4) * 64 + e];
+                const v4i im1 = stage[(fused_role(1, 1) * G * 4) * 64 + e];
+                // row sums of rows i0..i0+3, both K halves, per parity
+                const lds_v4i *const rs = (const lds_v4i *)(sstage + I * 64 + il0);
+                const v4i s0 = rs[0] + rs[8];
+                const v4i s1 = rs[D * 16] + rs[D * 16 + 8];
+                int p = i0 * (i0 + 1) / 2 + j;
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
                     const int i = i0 + m;
-                    const bool ok = qq < NQ && i < N && j <= i;
-                    old[k][m] = in_f[ok ? p : 0];
+                    if (i < N && (!diag || j <= i)) {
+                        const int re = (re0[m] >> 8) + (re1[m] >> 8);
+                        const int im = ((im0[m] + s0[m]) >> 8) + ((im1[m] + s1[m]) >> 8);
+                        int2 o = make_int2(0, 0);
+                        if constexpr (ACC == 1 && D > 3)
+                            o = old[kc][m];
+                        else if constexpr (ACC != 0)
+                            if (ACC == 1 || accumulate)
+                                o = in_f[p];
+                        out_f[p] = make_int2(re + o.x, im + o.y);
+                    }
                     p += i + 1;
                 }
+                // one quad at a time: hoisting the next quad's LDS reads
+                // above these stores would need registers the accumulators
+                // of later rounds still hold
+                __builtin_amdgcn_sched_barrier(0);
             }
-#pragma unroll
-            for (int k = 0; k < QPT; ++k) {
-                const int qq = tid + k * kMfmaThreads;
-                if (qq < NQ)
-                    emit(qq, [&](int m, int64_t) { return old[k][m]; });
-            }
-        }
-        __syncthreads();
-    }
+        });
+        // the next round overwrites the stage; after the last one the caller
+        // synchronises before it reuses LDS
+        if constexpr (rc + 1 < fused_rounds(D, TRI))
+            __syncthreads();
+    });
 }
 
 template <int D, bool TRI, int KC, int NBUF, int VEC, int MB = 0, int ACC = 2>
