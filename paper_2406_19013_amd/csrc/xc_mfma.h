@@ -66,6 +66,31 @@ constexpr bool half_uses_row(int D, bool tri, int h, int b)
             return true;
     return false;
 }
+// Epilogue rounds of G staged tiles: slot u of round rc holds tile
+// epilogue_slot_tile(...), or -1 if empty.  With an even G each round takes
+// G/2 tiles from each half of the region, so that the waves of both halves
+// free accumulator registers from the first round on; with an odd G tiles go
+// in order.
+constexpr int epilogue_slot_tile(int D, bool tri, int G, int rc, int u)
+{
+    const int NT = n_tiles(D, tri);
+    if (G % 2) {
+        const int t = rc * G + u;
+        return t < NT ? t : -1;
+    }
+    const int H = G / 2, h = u < H ? 0 : 1;
+    const int t = half_begin(D, tri, h) + rc * H + (u - h * H);
+    return t < half_end(D, tri, h) ? t : -1;
+}
+constexpr int epilogue_rounds(int D, bool tri, int G)
+{
+    if (G % 2)
+        return (n_tiles(D, tri) + G - 1) / G;
+    const int H = G / 2;
+    const int r0 = (half_end(D, tri, 0) - half_begin(D, tri, 0) + H - 1) / H;
+    const int r1 = (half_end(D, tri, 1) - half_begin(D, tri, 1) + H - 1) / H;
+    return r0 > r1 ? r0 : r1;
+}
 constexpr bool half_uses_col(int D, bool tri, int h, int b)
 {
     for (int t = half_begin(D, tri, h); t < half_end(D, tri, h); ++t)

@@ -324,36 +324,6 @@ constexpr int fused_smem_bytes(int D)
                : fused_epilogue_tiles(D) * 16384 + 2 * D * 256;
 }
 
-// Epilogue rounds: slot u of round rc holds tile fused_slot_tile(...), or -1.
-// With an even G each round takes G/2 tiles from each half, so that every
-// wave frees registers from the first round on; with an odd G tiles go in
-// order.
-constexpr int fused_slot_tile(int D, bool tri, int rc, int u)
-{
-    const int G = fused_epilogue_tiles(D), NT = n_tiles(D, tri);
-    if (G % 2) {
-        const int t = rc * G + u;
-        return t < NT ? t : -1;
-    }
-    const int H = G / 2, h = u < H ? 0 : 1;
-    const int t = half_begin(D, tri, h) + rc * H + (u - h * H);
-    return t < half_end(D, tri, h) ? t : -1;
-}
-constexpr int fused_rounds(int D, bool tri)
-{
-    int r = 0;
-    for (int t = 0; t < n_tiles(D, tri); ++t) {
-        bool found = false;
-        for (int rc = 0; !found; ++rc)
-            for (int u = 0; u < fused_epilogue_tiles(D); ++u)
-                if (fused_slot_tile(D, tri, rc, u) == t) {
-                    found = true;
-                    r = rc + 1 > r ? rc + 1 : r;
-                }
-    }
-    return r;
-}
-
 // Does half HALF compute the row sums of row block I (the half owning the
 // first tile of row I)?
 constexpr bool owns_rowsum(int D, bool tri, int half, int I)
@@ -557,10 +527,10 @@ __device__ __forceinline__ void mfma4f_region(uint8_t *smem, const uint8_t *__re
     const int2 *const in_f = acc_in + (int64_t)f * P;
     const int il0 = 8 * RQ + 4 * (elane >> 5);   // first row of the quad within its 32-row block
     const int jl = elane & 31;
-    static_for<0, fused_rounds(D, TRI)>([&](auto rc) {
+    static_for<0, epilogue_rounds(D, TRI, G)>([&](auto rc) {
         static_for<0, G>([&](auto uc) {
             constexpr int u = uc;
-            constexpr int t = fused_slot_tile(D, TRI, rc, u);
+            constexpr int t = epilogue_slot_tile(D, TRI, G, rc, u);
             if constexpr (t >= T0 && t < T1) {
                 static_for<0, 4>([&](auto rqc) {
                     constexpr int rq = rqc;
@@ -577,7 +547,7 @@ __device__ __forceinline__ void mfma4f_region(uint8_t *smem, const uint8_t *__re
         if constexpr (ACC == 1 && D > 3) {
             static_for<0, KQ>([&](auto kc) {
                 constexpr int u = PROD + 2 * kc;
-                constexpr int t = u < G ? fused_slot_tile(D, TRI, rc, u) : -1;
+                constexpr int t = u < G ? epilogue_slot_tile(D, TRI, G, rc, u) : -1;
                 if constexpr (t >= 0) {
                     constexpr int I = tile_I(D, TRI, t), J = tile_J(D, TRI, t);
                     const int i0 = (row_blk + I) * 32 + il0;
@@ -595,7 +565,7 @@ __device__ __forceinline__ void mfma4f_region(uint8_t *smem, const uint8_t *__re
         }
         static_for<0, KQ>([&](auto kc) {
             constexpr int u = PROD + 2 * kc;
-            constexpr int t = u < G ? fused_slot_tile(D, TRI, rc, u) : -1;
+            constexpr int t = u < G ? epilogue_slot_tile(D, TRI, G, rc, u) : -1;
             if constexpr (t >= 0) {
                 constexpr int I = tile_I(D, TRI, t), J = tile_J(D, TRI, t);
                 constexpr bool diag = TRI && I == J;
@@ -635,7 +605,7 @@ __device__ __forceinline__ void mfma4f_region(uint8_t *smem, const uint8_t *__re
         });
         // the next round overwrites the stage; after the last one the caller
         // synchronises before it reuses LDS
-        if constexpr (rc + 1 < fused_rounds(D, TRI))
+        if constexpr (rc + 1 < epilogue_rounds(D, TRI, G))
             __syncthreads();
     });
 }

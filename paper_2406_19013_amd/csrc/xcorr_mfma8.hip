@@ -148,10 +148,14 @@ __device__ __forceinline__ void k_step8(lds_u8 *const *addr, typename std::condi
 }
 
 constexpr int mfma8_nbuf() { return 4; }
-constexpr int mfma8_epilogue_tiles(int D) { return D <= 3 ? 4 : 6; }
-constexpr int mfma8_smem_bytes(int KC)
+// tiles per epilogue round; for D >= 4 the stage (4 roles x 8 tiles x 4 KB
+// plus the row sums, 131 KB) is larger than the 128 KB ring
+constexpr int mfma8_epilogue_tiles(int D) { return D <= 3 ? 4 : 8; }
+constexpr int mfma8_smem_bytes(int KC, int D)
 {
-    return mfma8_nbuf() * KC * kRow8;   // 128 KB at KC = 64; the epilogue stage reuses it
+    return mfma8_nbuf() * KC * kRow8 > 4 * mfma8_epilogue_tiles(D) * 4096 + 2 * D * 256
+               ? mfma8_nbuf() * KC * kRow8
+               : 4 * mfma8_epilogue_tiles(D) * 4096 + 2 * D * 256;
 }
 
 template <int D, bool TRI, bool F16, int KC, int NBUF, int VEC, int PROD, int PAR, int HALF>
@@ -267,91 +271,111 @@ __device__ __forceinline__ void mfma8_region(uint8_t *smem, const uint8_t *__res
 
     // Epilogue: Re = sum of the two parities' Re products, Im = the two Im
     // products (+ S_i on the int8 path), G tiles per round.  Stage layout as
-    // in the 4-bit path; the row sums follow the tile stage.
+    // in the 4-bit path; the row sums follow the tile stage.  A wave's quads
+    // are known at compile time: slots u = HALF, HALF + 2, ... of the round,
+    // row quad rq = PROD + 2 PAR, which is the wave's index mod 4.
     typedef __attribute__((address_space(3))) v4i lds_v4i;
     lds_v4i *const stage = (lds_v4i *)smem;
     int *const sstage = (int *)(smem + 4 * G * 4096);          // [parity][row block][64 lanes]
+    // lane offsets of the epilogue, from an opaque copy of the thread index so
+    // that none of them is computed before the K loop and held across it
+    int etid = threadIdx.x;
+    asm volatile("" : "+v"(etid));
+    const int elane = etid & 63;
     if constexpr (!F16 && PROD == 1) {
         static_for<0, D>([&](auto bc) {
             if constexpr (half_owns_rowsum(D, TRI, HALF, bc))
-                sstage[(PAR * D + bc) * 64 + lane] = rsum[bc];
+                sstage[(PAR * D + bc) * 64 + elane] = rsum[bc];
         });
     }
+    constexpr int RQ = PROD + 2 * PAR;
+    constexpr int KQ = (G + 1) / 2;
     const int64_t P = (int64_t)N * (N + 1) / 2;
-#pragma unroll
-    for (int t0 = 0; t0 < NT; t0 += G) {
-        // this wave's tiles of the round [t0, t0 + G)
-        static_for<T0, T1>([&](auto tc) {
-            constexpr int t = tc;
-            const int u = t - t0;
-            if (u >= 0 && u < G) {
-#pragma unroll
-                for (int rq = 0; rq < 4; ++rq) {
+    const int il0 = 8 * RQ + 4 * (elane >> 5);   // first row of the quad within its 32-row block
+    const int jl = elane & 31;
+    static_for<0, epilogue_rounds(D, TRI, G)>([&](auto rc) {
+        static_for<0, G>([&](auto uc) {
+            constexpr int u = uc;
+            constexpr int t = epilogue_slot_tile(D, TRI, G, rc, u);
+            if constexpr (t >= T0 && t < T1) {
+                static_for<0, 4>([&](auto rqc) {
+                    constexpr int rq = rqc;
                     if constexpr (F16)
-                        stage[((ROLE * G + u) * 4 + rq) * 64 + lane] = __builtin_bit_cast(
+                        stage[((ROLE * G + u) * 4 + rq) * 64 + elane] = __builtin_bit_cast(
                             v4i, v4f{acc[t - T0][4 * rq], acc[t - T0][4 * rq + 1], acc[t - T0][4 * rq + 2],
                                      acc[t - T0][4 * rq + 3]});
                     else
-                        stage[((ROLE * G + u) * 4 + rq) * 64 + lane] =
+                        stage[((ROLE * G + u) * 4 + rq) * 64 + elane] =
                             v4i{acc[t - T0][4 * rq], acc[t - T0][4 * rq + 1], acc[t - T0][4 * rq + 2],
                                 acc[t - T0][4 * rq + 3]};
-                }
+                });
             }
         });
         __syncthreads();
-        const int NQ = (NT - t0 < G ? NT - t0 : G) * 256;
-        for (int qq = tid; qq < NQ; qq += kMfmaThreads) {
-            const int u = qq >> 8, rq = (qq >> 6) & 3, ln = qq & 63;
-            const int t = t0 + u;
-            const int I = TRI ? tri_I_rt(t) : t / D;
-            const int J = TRI ? tri_J_rt(t) : t % D;
-            const int i0 = (row_blk + I) * 32 + 8 * rq + 4 * (ln >> 5);
-            const int j = (col_blk + J) * 32 + (ln & 31);
-            const int e = (u * 4 + rq) * 64 + ln;
-            const v4i re0 = stage[(role8(0, 0) * G * 4) * 64 + e];
-            const v4i re1 = stage[(role8(0, 1) * G * 4) * 64 + e];
-            const v4i im0 = stage[(role8(1, 0) * G * 4) * 64 + e];
-            const v4i im1 = stage[(role8(1, 1) * G * 4) * 64 + e];
-            int64_t p = (int64_t)i0 * (i0 + 1) / 2 + j;
+        static_for<0, KQ>([&](auto kc) {
+            constexpr int u = HALF + 2 * kc;
+            constexpr int t = u < G ? epilogue_slot_tile(D, TRI, G, rc, u) : -1;
+            if constexpr (t >= 0) {
+                constexpr int I = tile_I(D, TRI, t), J = tile_J(D, TRI, t);
+                constexpr bool diag = TRI && I == J;
+                const int i0 = (row_blk + I) * 32 + il0;
+                const int j = (col_blk + J) * 32 + jl;
+                const int e = (u * 4 + RQ) * 64 + elane;
+                const v4i re0 = stage[(role8(0, 0) * G * 4) * 64 + e];
+                const v4i re1 = stage[(role8(0, 1) * G * 4) * 64 + e];
+                const v4i im0 = stage[(role8(1, 0) * G * 4) * 64 + e];
+                const v4i im1 = stage[(role8(1, 1) * G * 4) * 64 + e];
+                int p = i0 * (i0 + 1) / 2 + j;
+                if constexpr (F16) {
+                    // whole-vector casts: a bit cast of one subscripted element
+                    // is not reliable in this compiler
+                    const v4f fr0 = __builtin_bit_cast(v4f, re0), fr1 = __builtin_bit_cast(v4f, re1);
+                    const v4f fi0 = __builtin_bit_cast(v4f, im0), fi1 = __builtin_bit_cast(v4f, im1);
+                    float2 *const dst = static_cast<float2 *>(acc_out) + (int64_t)f * P;
 #pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const int i = i0 + m;
-                if (i < N && j <= i) {
-                    if constexpr (F16) {
-                        // whole-vector casts: a bit cast of one subscripted
-                        // element is not reliable in this compiler
-                        const v4f fr0 = __builtin_bit_cast(v4f, re0), fr1 = __builtin_bit_cast(v4f, re1);
-                        const v4f fi0 = __builtin_bit_cast(v4f, im0), fi1 = __builtin_bit_cast(v4f, im1);
-                        float re = fr0[m] + fr1[m];
-                        float im = fi0[m] + fi1[m];
-                        float2 *dst = static_cast<float2 *>(acc_out) + (int64_t)f * P + p;
-                        if (accumulate) {
-                            const float2 o = *dst;
-                            re += o.x;
-                            im += o.y;
+                    for (int m = 0; m < 4; ++m) {
+                        const int i = i0 + m;
+                        if (i < N && (!diag || j <= i)) {
+                            float re = fr0[m] + fr1[m];
+                            float im = fi0[m] + fi1[m];
+                            if (accumulate) {
+                                const float2 o = dst[p];
+                                re += o.x;
+                                im += o.y;
+                            }
+                            dst[p] = make_float2(re, im);
                         }
-                        *dst = make_float2(re, im);
-                    } else {
-                        // row i's sum of real parts over both parities and k-halves
-                        const int il = i - (row_blk + I) * 32;
-                        const int S = sstage[(0 * D + I) * 64 + il] + sstage[(0 * D + I) * 64 + 32 + il] +
-                                      sstage[(1 * D + I) * 64 + il] + sstage[(1 * D + I) * 64 + 32 + il];
-                        int re = re0[m] + re1[m];
-                        int im = im0[m] + im1[m] + S;
-                        int2 *dst = static_cast<int2 *>(acc_out) + (int64_t)f * P + p;
-                        if (accumulate) {
-                            const int2 o = *dst;
-                            re += o.x;
-                            im += o.y;
+                        p += i + 1;
+                    }
+                } else {
+                    // rows i0..i0+3: sums of real parts over both parities and K halves
+                    const lds_v4i *const rs = (const lds_v4i *)(sstage + I * 64 + il0);
+                    const v4i S = rs[0] + rs[8] + rs[D * 16] + rs[D * 16 + 8];
+                    int2 *const dst = static_cast<int2 *>(acc_out) + (int64_t)f * P;
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        const int i = i0 + m;
+                        if (i < N && (!diag || j <= i)) {
+                            int re = re0[m] + re1[m];
+                            int im = im0[m] + im1[m] + S[m];
+                            if (accumulate) {
+                                const int2 o = dst[p];
+                                re += o.x;
+                                im += o.y;
+                            }
+                            dst[p] = make_int2(re, im);
                         }
-                        *dst = make_int2(re, im);
+                        p += i + 1;
                     }
                 }
-                p += i + 1;
+                // one quad at a time (registers: later rounds' accumulators)
+                __builtin_amdgcn_sched_barrier(0);
             }
-        }
-        __syncthreads();
-    }
+        });
+        // the next round overwrites the stage; the launch ends after the last
+        if constexpr (rc + 1 < epilogue_rounds(D, TRI, G))
+            __syncthreads();
+    });
 }
 
 template <int D, bool TRI, bool F16, int KC, int NBUF, int VEC>
@@ -377,8 +401,8 @@ void xc_mfma8_kernel(const uint8_t *__restrict__ volts, int64_t T, int F, int N,
                      int nitems, void *__restrict__ acc_out, int accumulate)
 {
     constexpr int NBUF = mfma8_nbuf();
-    __shared__ __attribute__((aligned(1024))) uint8_t smem[mfma8_smem_bytes(KC)];
-    static_assert(4 * mfma8_epilogue_tiles(D) * 4096 + 2 * D * 64 * 4 <= mfma8_smem_bytes(KC), "stage fits");
+    __shared__ __attribute__((aligned(1024))) uint8_t smem[mfma8_smem_bytes(KC, D)];
+    static_assert(4 * mfma8_epilogue_tiles(D) * 4096 + 2 * D * 64 * 4 <= mfma8_smem_bytes(KC, D), "stage fits");
 
     const int item = xcd_item();
     if (item >= nitems)
