@@ -108,6 +108,22 @@ __device__ __forceinline__ void wait_vmcnt()
     __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
+// Wait until the chunk before the last r chunks a wave issued has arrived:
+// at most r (wave-uniform, 0 <= r <= MAXR) chunks of LOADS loads each may
+// still be outstanding.
+template <int LOADS, int MAXR>
+__device__ __forceinline__ void wait_vmcnt_chunks(int r)
+{
+    if constexpr (MAXR > 0) {
+        if (r >= MAXR)
+            wait_vmcnt<LOADS * MAXR>();
+        else
+            wait_vmcnt_chunks<LOADS, MAXR - 1>(r);
+    } else {
+        wait_vmcnt<0>();
+    }
+}
+
 constexpr int kBufferOutOfRange = (int)0xFFFFFFF0;  // any offset >= num_records reads 0
 
 // Cache policy of the LDS-DMA input loads (sc0 | nt | sc1): every input byte

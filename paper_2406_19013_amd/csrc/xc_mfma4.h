@@ -389,7 +389,6 @@ __device__ __forceinline__ void mfma4f_region(uint8_t *smem, const uint8_t *__re
                                               const BlockTable *bt = nullptr)
 {
     static_assert(!MB || (VEC && KC == 64), "block tables feed the LDS-DMA path with 64-row chunks");
-    constexpr int NT = n_tiles(D, TRI);
     constexpr int T0 = half_begin(D, TRI, HALF), T1 = half_end(D, TRI, HALF);
     constexpr int NB = TRI ? D : 2 * D;
     constexpr int BUF = KC * kRowBytes;
@@ -403,7 +402,7 @@ __device__ __forceinline__ void mfma4f_region(uint8_t *smem, const uint8_t *__re
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));   // keep per-lane offsets inside an enclosing item loop
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    constexpr int WAVE = 4 * PROD + 2 * PAR + (HALF ^ PROD);   // the wave that runs this role
     const int g = lane >> 4, q = lane & 15;
     lds_u8 *const ring = (lds_u8 *)smem;
 
@@ -417,7 +416,7 @@ __device__ __forceinline__ void mfma4f_region(uint8_t *smem, const uint8_t *__re
     int voff[LOADS];
 #pragma unroll
     for (int k = 0; k < LOADS; ++k) {
-        const int U = (wave * LOADS + k) * 64 + lane;
+        const int U = (WAVE * LOADS + k) * 64 + lane;
         const int r = U >> 4;
         const int p = (U & 15) ^ ((r & 7) << 1);
         const int i0 = p < 2 * D ? row_blk * 32 + 16 * p : col_blk * 32 + 16 * (p - 2 * D);
@@ -435,28 +434,44 @@ __device__ __forceinline__ void mfma4f_region(uint8_t *smem, const uint8_t *__re
         rsum[b] = 0;
 
     const int nchunks = (int)((T + KC - 1) / KC);
-    auto issue = [&](int c, int bufi) {
-        const int64_t rows = min((int64_t)KC, T - (int64_t)c * KC);
-        const uint8_t *base;
-        if constexpr (MB) {
-            const int blk = c / bt->chunks_per_block;
-            base = bt->p[blk] + (int64_t)(c - blk * bt->chunks_per_block) * KC * row_bytes;
-        } else {
-            base = volts + (int64_t)c * KC * row_bytes;
-        }
-        __amdgpu_buffer_rsrc_t rsrc =
-            __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, (int)(rows * row_bytes), 0x00020000);
-        lds_u8 *dst = ring + bufi * BUF + wave * LOADS * 1024;
+    // DMA state of the next chunk to issue, wave-uniform: its source, the
+    // input bytes left from there (MB = 0), its block and position in that
+    // block (MB = 1).  Chunks are issued strictly in order.
+    const int64_t chunk_bytes = KC * row_bytes;
+    const uint8_t *nsrc;
+    int64_t nleft = 0;
+    int nblk = 0, nin = 0;
+    if constexpr (MB)
+        nsrc = bt->p[0];
+    else {
+        nsrc = volts;
+        nleft = T * row_bytes;
+    }
+    auto issue_next = [&](int bufi) {
+        // block-table chunks are always whole; the input's last may be short
+        const int records = MB ? (int)chunk_bytes : (int)(nleft < chunk_bytes ? nleft : chunk_bytes);
+        __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc((void *)nsrc, (short)0, records, 0x00020000);
+        lds_u8 *dst = ring + bufi * BUF + WAVE * LOADS * 1024;
 #pragma unroll
         for (int k = 0; k < LOADS; ++k)
             __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (__attribute__((address_space(3))) void *)(dst + k * 1024),
                                                      16, voff[k], 0, 0, kStreamLoadPolicy);
+        nsrc += chunk_bytes;
+        if constexpr (MB) {
+            if (++nin == bt->chunks_per_block) {
+                nin = 0;
+                if (++nblk < kMaxFusedBlocks)
+                    nsrc = bt->p[nblk];
+            }
+        } else {
+            nleft -= chunk_bytes;
+        }
     };
     auto fill_sync = [&](int c, int bufi) {
         lds_u8 *dst = ring + bufi * BUF;
 #pragma unroll
         for (int k = 0; k < LOADS; ++k) {
-            const int U = (wave * LOADS + k) * 64 + lane;
+            const int U = (WAVE * LOADS + k) * 64 + lane;
             const int r = U >> 4;
             const int p = (U & 15) ^ ((r & 7) << 1);
             const int i0 = p < 2 * D ? row_blk * 32 + 16 * p : col_blk * 32 + 16 * (p - 2 * D);
@@ -465,30 +480,9 @@ __device__ __forceinline__ void mfma4f_region(uint8_t *smem, const uint8_t *__re
             *(__attribute__((address_space(3))) v4i *)(dst + U * 16) = val;
         }
     };
-
-    if constexpr (VEC) {
-#pragma unroll
-        for (int c = 0; c < NBUF - 1; ++c)
-            if (c < nchunks)
-                issue(c, c);
-    }
-    int bufc = 0;
-    for (int c = 0; c < nchunks; ++c) {
-        if constexpr (VEC) {
-            if (c + NBUF - 2 < nchunks)
-                wait_vmcnt<LOADS * (NBUF - 2)>();
-            else
-                wait_vmcnt<0>();
-            barrier_no_fence();
-            if (c + NBUF - 1 < nchunks)
-                issue(c + NBUF - 1, bufc == 0 ? NBUF - 1 : bufc - 1);
-        } else {
-            __syncthreads();
-            fill_sync(c, bufc);
-            __syncthreads();
-        }
+    auto compute = [&](int bufi) {
         lds_u8 *addr[NB];
-        lds_u8 *const cb = ring + bufc * BUF + row_off;
+        lds_u8 *const cb = ring + bufi * BUF + row_off;
 #pragma unroll
         for (int b = 0; b < NB; ++b)
             addr[b] = cb + colo[b];
@@ -496,7 +490,40 @@ __device__ __forceinline__ void mfma4f_region(uint8_t *smem, const uint8_t *__re
         static_for<0, KC / 64>([&](auto kc) {
             k_step_fused<D, TRI, PROD, HALF, (2 * kc + PAR) * 32 * kRowBytes>(addr, acc, rsum);
         });
-        bufc = bufc + 1 == NBUF ? 0 : bufc + 1;
+    };
+
+    int bufc = 0;
+    if constexpr (VEC) {
+#pragma unroll
+        for (int c = 0; c < NBUF - 1; ++c)
+            if (c < nchunks)
+                issue_next(c);
+        int c = 0;
+        // steady state: chunk c is complete when this wave has at most the
+        // NBUF - 2 chunks issued after it outstanding; then chunk c + NBUF - 1
+        // goes into the slot the previous iteration read
+        for (; c + NBUF - 1 < nchunks; ++c) {
+            wait_vmcnt<LOADS * (NBUF - 2)>();
+            barrier_no_fence();
+            issue_next(bufc == 0 ? NBUF - 1 : bufc - 1);
+            compute(bufc);
+            bufc = bufc + 1 == NBUF ? 0 : bufc + 1;
+        }
+        // tail: everything is issued; nchunks - 1 - c chunks follow chunk c
+        for (; c < nchunks; ++c) {
+            wait_vmcnt_chunks<LOADS, NBUF - 2>(nchunks - 1 - c);
+            barrier_no_fence();
+            compute(bufc);
+            bufc = bufc + 1 == NBUF ? 0 : bufc + 1;
+        }
+    } else {
+        for (int c = 0; c < nchunks; ++c) {
+            __syncthreads();
+            fill_sync(c, bufc);
+            __syncthreads();
+            compute(bufc);
+            bufc = bufc + 1 == NBUF ? 0 : bufc + 1;
+        }
     }
     __syncthreads();
 
