@@ -164,7 +164,6 @@ __device__ __forceinline__ void mfma8_region(uint8_t *smem, const uint8_t *__res
                                              void *__restrict__ acc_out, int accumulate)
 {
     using AccT = typename std::conditional<F16, v16f, v16i>::type;
-    constexpr int NT = n_tiles(D, TRI);
     constexpr int T0 = half_begin(D, TRI, HALF), T1 = half_end(D, TRI, HALF);
     constexpr int NB = TRI ? D : 2 * D;
     constexpr int BUF = KC * kRow8;
@@ -174,9 +173,8 @@ __device__ __forceinline__ void mfma8_region(uint8_t *smem, const uint8_t *__res
     static_assert(LOADS * kMfmaThreads == KC * 32, "chunk must be a whole number of wave loads");
     static_assert(KC % 32 == 0, "a chunk holds whole pairs of 16-sample K steps");
 
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int lane = threadIdx.x & 63;
+    constexpr int WAVE = PROD + 2 * PAR + 4 * HALF;   // the wave that runs this role
     const int g = lane >> 4, q = lane & 15;
     lds_u8 *const ring = (lds_u8 *)smem;
 
@@ -193,7 +191,7 @@ __device__ __forceinline__ void mfma8_region(uint8_t *smem, const uint8_t *__res
     int voff[LOADS];
 #pragma unroll
     for (int k = 0; k < LOADS; ++k) {
-        const int U = (wave * LOADS + k) * 64 + lane;
+        const int U = (WAVE * LOADS + k) * 64 + lane;
         const int r = U >> 5;
         const int p = (U & 31) ^ ((r & 3) << 2);
         const int i0 = p < 4 * D ? row_blk * 32 + 8 * p : col_blk * 32 + 8 * (p - 4 * D);
@@ -211,21 +209,27 @@ __device__ __forceinline__ void mfma8_region(uint8_t *smem, const uint8_t *__res
         rsum[b] = 0;
 
     const int nchunks = (int)((T + KC - 1) / KC);
-    auto issue = [&](int c, int bufi) {
-        const int64_t rows = min((int64_t)KC, T - (int64_t)c * KC);
-        __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
-            (void *)(volts + (int64_t)c * KC * row_bytes), (short)0, (int)(rows * row_bytes), 0x00020000);
-        lds_u8 *dst = ring + bufi * BUF + wave * LOADS * 1024;
+    // DMA state of the next chunk to issue (wave-uniform): its source and the
+    // input bytes left from there; chunks are issued strictly in order
+    const int64_t chunk_bytes = KC * row_bytes;
+    const uint8_t *nsrc = volts;
+    int64_t nleft = T * row_bytes;
+    auto issue_next = [&](int bufi) {
+        const int records = (int)(nleft < chunk_bytes ? nleft : chunk_bytes);
+        __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc((void *)nsrc, (short)0, records, 0x00020000);
+        lds_u8 *dst = ring + bufi * BUF + WAVE * LOADS * 1024;
 #pragma unroll
         for (int k = 0; k < LOADS; ++k)
             __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (__attribute__((address_space(3))) void *)(dst + k * 1024),
                                                      16, voff[k], 0, 0, kStreamLoadPolicy);
+        nsrc += chunk_bytes;
+        nleft -= chunk_bytes;
     };
     auto fill_sync = [&](int c, int bufi) {
         lds_u8 *dst = ring + bufi * BUF;
 #pragma unroll
         for (int k = 0; k < LOADS; ++k) {
-            const int U = (wave * LOADS + k) * 64 + lane;
+            const int U = (WAVE * LOADS + k) * 64 + lane;
             const int r = U >> 5;
             const int p = (U & 31) ^ ((r & 3) << 2);
             const int i0 = p < 4 * D ? row_blk * 32 + 8 * p : col_blk * 32 + 8 * (p - 4 * D);
@@ -234,30 +238,9 @@ __device__ __forceinline__ void mfma8_region(uint8_t *smem, const uint8_t *__res
             *(__attribute__((address_space(3))) v4i *)(dst + U * 16) = val;
         }
     };
-
-    if constexpr (VEC) {
-#pragma unroll
-        for (int c = 0; c < NBUF - 1; ++c)
-            if (c < nchunks)
-                issue(c, c);
-    }
-    int bufc = 0;
-    for (int c = 0; c < nchunks; ++c) {
-        if constexpr (VEC) {
-            if (c + NBUF - 2 < nchunks)
-                wait_vmcnt<LOADS * (NBUF - 2)>();
-            else
-                wait_vmcnt<0>();
-            barrier_no_fence();
-            if (c + NBUF - 1 < nchunks)
-                issue(c + NBUF - 1, bufc == 0 ? NBUF - 1 : bufc - 1);
-        } else {
-            __syncthreads();
-            fill_sync(c, bufc);
-            __syncthreads();
-        }
+    auto compute = [&](int bufi) {
         lds_u8 *addr[NB];
-        lds_u8 *const cb = ring + bufc * BUF + row_off;
+        lds_u8 *const cb = ring + bufi * BUF + row_off;
 #pragma unroll
         for (int b = 0; b < NB; ++b)
             addr[b] = cb + colo[b];
@@ -265,7 +248,38 @@ __device__ __forceinline__ void mfma8_region(uint8_t *smem, const uint8_t *__res
         k_step8<D, TRI, F16, PROD, HALF, PAR * 16 * kRow8>(addr, acc, rsum);
         if constexpr (KC == 64)
             k_step8<D, TRI, F16, PROD, HALF, (PAR + 2) * 16 * kRow8>(addr, acc, rsum);
-        bufc = bufc + 1 == NBUF ? 0 : bufc + 1;
+    };
+
+    int bufc = 0;
+    if constexpr (VEC) {
+#pragma unroll
+        for (int c = 0; c < NBUF - 1; ++c)
+            if (c < nchunks)
+                issue_next(c);
+        // one loop body (two copies of it cost registers): chunk c is
+        // complete when at most the chunks this wave issued after it are
+        // outstanding; while chunks remain, chunk c + NBUF - 1 goes into the
+        // slot the previous iteration read
+        for (int c = 0; c < nchunks; ++c) {
+            const int after = nchunks - 1 - c;
+            if (after >= NBUF - 2)
+                wait_vmcnt<LOADS * (NBUF - 2)>();
+            else
+                wait_vmcnt_chunks<LOADS, NBUF - 3>(after);
+            barrier_no_fence();
+            if (after >= NBUF - 1)
+                issue_next(bufc == 0 ? NBUF - 1 : bufc - 1);
+            compute(bufc);
+            bufc = bufc + 1 == NBUF ? 0 : bufc + 1;
+        }
+    } else {
+        for (int c = 0; c < nchunks; ++c) {
+            __syncthreads();
+            fill_sync(c, bufc);
+            __syncthreads();
+            compute(bufc);
+            bufc = bufc + 1 == NBUF ? 0 : bufc + 1;
+        }
     }
     __syncthreads();
 
