@@ -382,7 +382,11 @@ __device__ __forceinline__ void k_step_fused(lds_u8 *const *addr, v16i *acc, int
 // progress, or the accumulators when the result goes to a separate buffer).
 // ACC: 0 = the launch overwrites, 1 = it accumulates (the running sums are
 // loaded in batches), 2 = the `accumulate` argument decides (per element).
-template <int D, bool TRI, int KC, int NBUF, int VEC, int PROD, int PAR, int HALF, int MB = 0, int ACC = 2>
+// COMPACT: one copy of the K loop and a runtime loop over the epilogue's
+// tiles, for the persistent kernel that holds every tile shape (its code
+// would otherwise outgrow the instruction cache); the other kernels unroll.
+template <int D, bool TRI, int KC, int NBUF, int VEC, int PROD, int PAR, int HALF, int MB = 0, int ACC = 2,
+          bool COMPACT = false>
 __device__ __forceinline__ void mfma4f_region(uint8_t *smem, const uint8_t *__restrict__ volts,
                                               int64_t T, int F, int N, int f, int row_blk, int col_blk,
                                               int2 *acc_out, const int2 *acc_in, int accumulate,
@@ -498,23 +502,38 @@ __device__ __forceinline__ void mfma4f_region(uint8_t *smem, const uint8_t *__re
         for (int c = 0; c < NBUF - 1; ++c)
             if (c < nchunks)
                 issue_next(c);
-        int c = 0;
-        // steady state: chunk c is complete when this wave has at most the
-        // NBUF - 2 chunks issued after it outstanding; then chunk c + NBUF - 1
-        // goes into the slot the previous iteration read
-        for (; c + NBUF - 1 < nchunks; ++c) {
-            wait_vmcnt<LOADS * (NBUF - 2)>();
-            barrier_no_fence();
-            issue_next(bufc == 0 ? NBUF - 1 : bufc - 1);
-            compute(bufc);
-            bufc = bufc + 1 == NBUF ? 0 : bufc + 1;
-        }
-        // tail: everything is issued; nchunks - 1 - c chunks follow chunk c
-        for (; c < nchunks; ++c) {
-            wait_vmcnt_chunks<LOADS, NBUF - 2>(nchunks - 1 - c);
-            barrier_no_fence();
-            compute(bufc);
-            bufc = bufc + 1 == NBUF ? 0 : bufc + 1;
+        if constexpr (COMPACT) {
+            for (int c = 0; c < nchunks; ++c) {
+                const int after = nchunks - 1 - c;   // chunks issued after chunk c, at most
+                if (after >= NBUF - 2)
+                    wait_vmcnt<LOADS * (NBUF - 2)>();
+                else
+                    wait_vmcnt_chunks<LOADS, NBUF - 3>(after);
+                barrier_no_fence();
+                if (after >= NBUF - 1)
+                    issue_next(bufc == 0 ? NBUF - 1 : bufc - 1);
+                compute(bufc);
+                bufc = bufc + 1 == NBUF ? 0 : bufc + 1;
+            }
+        } else {
+            int c = 0;
+            // steady state: chunk c is complete when this wave has at most the
+            // NBUF - 2 chunks issued after it outstanding; then chunk c + NBUF - 1
+            // goes into the slot the previous iteration read
+            for (; c + NBUF - 1 < nchunks; ++c) {
+                wait_vmcnt<LOADS * (NBUF - 2)>();
+                barrier_no_fence();
+                issue_next(bufc == 0 ? NBUF - 1 : bufc - 1);
+                compute(bufc);
+                bufc = bufc + 1 == NBUF ? 0 : bufc + 1;
+            }
+            // tail: everything is issued; nchunks - 1 - c chunks follow chunk c
+            for (; c < nchunks; ++c) {
+                wait_vmcnt_chunks<LOADS, NBUF - 2>(nchunks - 1 - c);
+                barrier_no_fence();
+                compute(bufc);
+                bufc = bufc + 1 == NBUF ? 0 : bufc + 1;
+            }
         }
     } else {
         for (int c = 0; c < nchunks; ++c) {
@@ -554,6 +573,63 @@ __device__ __forceinline__ void mfma4f_region(uint8_t *smem, const uint8_t *__re
     const int2 *const in_f = acc_in + (int64_t)f * P;
     const int il0 = 8 * RQ + 4 * (elane >> 5);   // first row of the quad within its 32-row block
     const int jl = elane & 31;
+    if constexpr (COMPACT) {
+        // G tiles per round, in order
+        constexpr int NT = n_tiles(D, TRI);
+#pragma unroll 1
+        for (int t0 = 0; t0 < NT; t0 += G) {
+            static_for<T0, T1>([&](auto tc) {
+                constexpr int t = tc;
+                const int u = t - t0;
+                if (u >= 0 && u < G) {
+                    static_for<0, 4>([&](auto rqc) {
+                        constexpr int rq = rqc;
+                        stage[((ROLE * G + u) * 4 + rq) * 64 + elane] =
+                            v4i{acc[t - T0][4 * rq], acc[t - T0][4 * rq + 1], acc[t - T0][4 * rq + 2],
+                                acc[t - T0][4 * rq + 3]};
+                    });
+                }
+            });
+            __syncthreads();
+            const int NQ = (NT - t0 < G ? NT - t0 : G) * 256;   // (tile, rq, lane) quads this round
+#pragma unroll 1
+            for (int qq = etid; qq < NQ; qq += kMfmaThreads) {
+                const int u = qq >> 8, rq = (qq >> 6) & 3, ln = qq & 63;
+                const int t = t0 + u;
+                const int I = TRI ? tri_I_rt(t) : t / D;
+                const int J = TRI ? tri_J_rt(t) : t % D;
+                const int ql0 = 8 * rq + 4 * (ln >> 5);
+                const int i0 = (row_blk + I) * 32 + ql0;
+                const int j = (col_blk + J) * 32 + (ln & 31);
+                const int e = (u * 4 + rq) * 64 + ln;
+                const v4i re0 = stage[(fused_role(0, 0) * G * 4) * 64 + e];
+                const v4i re1 = stage[(fused_role(0, 1) * G * 4) * 64 + e];
+                const v4i im0 = stage[(fused_role(1, 0) * G * 4) * 64 + e];
+                const v4i im1 = stage[(fused_role(1, 1) * G * 4) * 64 + e];
+                const lds_v4i *const rs = (const lds_v4i *)(sstage + I * 64 + ql0);
+                const v4i s0 = rs[0] + rs[8];
+                const v4i s1 = rs[D * 16] + rs[D * 16 + 8];
+                int p = i0 * (i0 + 1) / 2 + j;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const int i = i0 + m;
+                    if (i < N && j <= i) {
+                        const int re = (re0[m] >> 8) + (re1[m] >> 8);
+                        const int im = ((im0[m] + s0[m]) >> 8) + ((im1[m] + s1[m]) >> 8);
+                        int2 o = make_int2(0, 0);
+                        if constexpr (ACC != 0)
+                            if (ACC == 1 || accumulate)
+                                o = in_f[p];
+                        out_f[p] = make_int2(re + o.x, im + o.y);
+                    }
+                    p += i + 1;
+                }
+            }
+            if (t0 + G < NT)
+                __syncthreads();
+        }
+        return;
+    }
     static_for<0, epilogue_rounds(D, TRI, G)>([&](auto rc) {
         static_for<0, G>([&](auto uc) {
             constexpr int u = uc;
@@ -637,7 +713,7 @@ __device__ __forceinline__ void mfma4f_region(uint8_t *smem, const uint8_t *__re
     });
 }
 
-template <int D, bool TRI, int KC, int NBUF, int VEC, int MB = 0, int ACC = 2>
+template <int D, bool TRI, int KC, int NBUF, int VEC, int MB = 0, int ACC = 2, bool COMPACT = false>
 __device__ __forceinline__ void mfma4f_dispatch(uint8_t *smem, const uint8_t *__restrict__ volts,
                                                 int64_t T, int F, int N, int f, int row_blk, int col_blk,
                                                 int2 *acc_out, const int2 *acc_in, int accumulate,
@@ -646,7 +722,8 @@ __device__ __forceinline__ void mfma4f_dispatch(uint8_t *smem, const uint8_t *__
     switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {
 #define XC_CASE(W)                                                                                     \
     case W:                                                                                            \
-        mfma4f_region<D, TRI, KC, NBUF, VEC, ((W) >> 2), (((W) >> 1) & 1), (((W) & 1) ^ ((W) >> 2)), MB, ACC>( \
+        mfma4f_region<D, TRI, KC, NBUF, VEC, ((W) >> 2), (((W) >> 1) & 1), (((W) & 1) ^ ((W) >> 2)), MB, ACC, \
+                      COMPACT>(                                                                         \
             smem, volts, T, F, N, f, row_blk, col_blk, acc_out, acc_in, accumulate, bt);               \
         break;
         XC_CASE(0) XC_CASE(1) XC_CASE(2) XC_CASE(3) XC_CASE(4) XC_CASE(5) XC_CASE(6) XC_CASE(7)

@@ -42,12 +42,12 @@ __device__ __forceinline__ void batch_item(uint8_t *smem, const BatchArray &A, i
     const int f = local / A.regions;
     const int r = local - f * A.regions;
     if (r < A.nseg) {
-        mfma4f_dispatch<D, true, kBatchKC, NBUF, VEC>(smem, A.volts, A.T, A.F, A.N, f, r * D, r * D, A.acc,
+        mfma4f_dispatch<D, true, kBatchKC, NBUF, VEC, 0, 2, true>(smem, A.volts, A.T, A.F, A.N, f, r * D, r * D, A.acc,
                                                       A.acc, A.accumulate);
     } else if constexpr (D <= 4) {
         int a, b;
         rect_ab(r - A.nseg, a, b);
-        mfma4f_dispatch<D, false, kBatchKC, NBUF, VEC>(smem, A.volts, A.T, A.F, A.N, f, a * D, b * D, A.acc,
+        mfma4f_dispatch<D, false, kBatchKC, NBUF, VEC, 0, 2, true>(smem, A.volts, A.T, A.F, A.N, f, a * D, b * D, A.acc,
                                                        A.acc, A.accumulate);
     }
 }
