@@ -234,7 +234,8 @@ int xcorr_autotune(const xcorr_config *cfg, void *d_scratch, size_t scratch_byte
  * blocks must stay valid until the streams pass them.
  *
  * xcorr_pipe_query : ring bytes (n_slots slots of 256-byte-rounded blocks).
- * xcorr_pipe_init  : ctx borrowed; d_ring may be NULL for device blocks only.
+ * xcorr_pipe_init  : ctx borrowed; d_ring may be NULL for device blocks only;
+ *   dump_every = 0: dumps only through xcorr_pipe_dump.
  *   Errors: XCORR_E_INVAL, XCORR_E_NOMEM (short or misaligned ring),
  *   XCORR_E_OVERFLOW (dump_every * block_samples > max_samples_per_dump).
  *
@@ -263,9 +264,74 @@ int xcorr_pipe_reset_latency(xcorr_pipe *p);
  * until they are ingested; call xcorr_pipe_drain before xcorr_pipe_destroy
  * (destroy drops held blocks). */
 int xcorr_pipe_set_fuse(xcorr_pipe *p, int fuse);
+/* End the integration now (sequence-aligned integrations, e.g. on an
+ * XCORR_EV_DUMP event): ingest any held blocks, dump into d_out on
+ * compute_stream as xcorr_dump does (n_integrated / n_gaps may be NULL) and
+ * restart the count of dump_every.  With dump_every = 0 at init the pipe never
+ * dumps by itself; an integration is then bounded only by the context's
+ * max_samples_per_dump (an ingest past it fails with XCORR_E_OVERFLOW).
+ * Errors: XCORR_E_INVAL (NULL pipe or d_out), as xcorr_dump. */
+int xcorr_pipe_dump(xcorr_pipe *p, void *d_out, int64_t *n_integrated, uint64_t *n_gaps);
 int xcorr_pipe_destroy(xcorr_pipe *p);
 int xcorr_admit(const xcorr_config *cfgs, int n, const int64_t *block_samples, const int32_t *n_slots,
                 size_t budget_bytes, int32_t *admitted, size_t *used_bytes);
+
+/*
+ * Block reassembly by sequence number (the nodes' packet counter; all nodes
+ * start integrating at the same counter value so that their integrations
+ * cover the same span and the calibration noise source's on/off pattern
+ * falls inside one integration: Sections 2.2 and 2.3).  Pure host code, no
+ * device call; a reorder object is not thread-safe.
+ *
+ * Integration j covers sequence numbers [seq_origin + j*blocks_per_dump,
+ * seq_origin + (j+1)*blocks_per_dump).  xcorr_reorder_push takes one arriving
+ * block (`block` is an opaque handle, returned untouched) and writes to
+ * events[0..*n_events) what that arrival settles, in sequence order:
+ *   XCORR_EV_BLOCK  release block `seq` (feed it to the correlator now);
+ *   XCORR_EV_GAP    sequence numbers [seq, seq + n_blocks) are missing (one
+ *                   run never crosses an integration boundary);
+ *   XCORR_EV_DUMP   integration `integration` (first sequence number `seq`)
+ *                   is complete: n_blocks arrived, n_missing did not; valid =
+ *                   (n_missing <= max_missing).  Integrations of which no
+ *                   block arrived end without any event.
+ * A hole is declared missing once a block `window` or more sequence numbers
+ * beyond it has arrived (window 0: no reordering).  Blocks before
+ * seq_origin, blocks whose sequence number is already settled (late) and
+ * duplicates of a held block are dropped and counted.  xcorr_reorder_flush
+ * settles everything held (holes between held blocks become gaps) and, with
+ * to_boundary != 0, declares the rest of the current integration missing so
+ * that it ends.  `events` must hold xcorr_reorder_max_events(window) entries
+ * (4 window + 8), the most one call can produce.
+ * Errors: XCORR_E_INVAL (NULL arguments; blocks_per_dump outside [1, 2^30],
+ * window outside [0, 2^20], max_missing < 0), XCORR_E_NOMEM (events too
+ * short, checked before any state changes; host allocation).
+ */
+typedef struct xcorr_reorder xcorr_reorder;
+enum { XCORR_EV_BLOCK = 1, XCORR_EV_GAP = 2, XCORR_EV_DUMP = 3 };
+typedef struct {
+    int32_t kind;        /* XCORR_EV_* */
+    int32_t n_blocks;    /* BLOCK: 1; GAP: run length; DUMP: blocks that arrived */
+    int32_t n_missing;   /* DUMP: blocks declared missing */
+    int32_t valid;       /* DUMP: n_missing <= max_missing */
+    uint64_t seq;        /* BLOCK, GAP: first sequence number; DUMP: the integration's first */
+    int64_t integration; /* integration index of seq */
+    const void *block;   /* BLOCK: the handle given to xcorr_reorder_push */
+} xcorr_event;
+typedef struct {
+    int64_t received, released, missing, late, duplicate, before_origin, held;
+    int64_t integrations, invalid_integrations, empty_integrations;
+    uint64_t next_seq;   /* first sequence number not yet settled */
+} xcorr_reorder_stats_t;
+
+int32_t xcorr_reorder_max_events(int32_t window);
+int xcorr_reorder_init(int64_t blocks_per_dump, int32_t window, int32_t max_missing, uint64_t seq_origin,
+                       xcorr_reorder **out);
+int xcorr_reorder_push(xcorr_reorder *r, uint64_t seq, const void *block, xcorr_event *events, int32_t max_events,
+                       int32_t *n_events);
+int xcorr_reorder_flush(xcorr_reorder *r, int32_t to_boundary, xcorr_event *events, int32_t max_events,
+                        int32_t *n_events);
+int xcorr_reorder_stats(const xcorr_reorder *r, xcorr_reorder_stats_t *out);
+int xcorr_reorder_destroy(xcorr_reorder *r);
 
 const char *xcorr_strerror(int code);
 /* Detail of the last XCORR_E_HIP / XCORR_E_DEVICE on this thread. */

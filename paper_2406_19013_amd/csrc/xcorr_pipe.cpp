@@ -1,7 +1,7 @@
 // Streaming runtime of the C ABI: a ring of device block slots between a
 // copy stream (host -> device transfers) and a compute stream (ingest, and a
-// dump every `dump_every` blocks), with per-block latency taken from HIP
-// events; plus admission of arrays against a device-memory budget.
+// dump every `dump_every` blocks or on request), with per-block latency taken
+// from HIP events; plus admission of arrays against a device-memory budget.
 //
 // The paper's X-engine node runs a ring buffer of received packets feeding
 // the correlator, which integrates and hands each integration to an output
@@ -125,7 +125,7 @@ size_t round256(size_t x) { return (x + 255) / 256 * 256; }
 
 // Ingest the held device blocks as one group (and dump when asked), under one
 // latency record.
-int flush_held(xcorr_pipe *p, void *d_out, bool dump)
+int flush_held(xcorr_pipe *p, void *d_out, bool dump, int64_t *n_integrated = nullptr, uint64_t *n_gaps = nullptr)
 {
     if (p->held.empty() && !dump)
         return XCORR_OK;
@@ -144,7 +144,7 @@ int flush_held(xcorr_pipe *p, void *d_out, bool dump)
         p->held.clear();
     }
     if (rc == XCORR_OK && dump)
-        rc = xcorr_dump(p->ctx, d_out, nullptr, nullptr, p->compute);
+        rc = xcorr_dump(p->ctx, d_out, n_integrated, n_gaps, p->compute);
     if (rc) {
         p->spare.push_back(r);
         return rc;
@@ -178,8 +178,8 @@ int xcorr_pipe_init(xcorr_ctx *ctx, int n_slots, int64_t block_samples, int64_t 
     int rc = xcorr_pipe_query(ctx, n_slots, block_samples, &need);
     if (rc)
         return rc;
-    if (!out || dump_every < 1)
-        return api_error(XCORR_E_INVAL, "out is NULL or dump_every < 1");
+    if (!out || dump_every < 0)
+        return api_error(XCORR_E_INVAL, "out is NULL or dump_every < 0");
     if (dump_every > xc::ctx_shape(ctx).max_samples_per_dump / block_samples)
         return api_error(XCORR_E_OVERFLOW, "dump_every blocks exceed the context's max_samples_per_dump");
     if (n_slots > 1024)
@@ -221,7 +221,7 @@ int xcorr_pipe_push(xcorr_pipe *p, const void *block, int on_host, uint64_t seq,
         return api_error(XCORR_E_INVAL, "pipe or block is NULL");
     if (on_host && !p->ring)
         return api_error(XCORR_E_INVAL, "host blocks need a ring");
-    const bool dump_due = p->since_dump + 1 >= p->dump_every;
+    const bool dump_due = p->dump_every > 0 && p->since_dump + 1 >= p->dump_every;
     if (dump_due && !d_out)
         return api_error(XCORR_E_INVAL, "this block completes an integration: d_out is required");
     if (!on_host && p->fuse > 1) {
@@ -323,6 +323,18 @@ int xcorr_pipe_push(xcorr_pipe *p, const void *block, int on_host, uint64_t seq,
     if (dumped)
         *dumped = did;
     return XCORR_OK;
+}
+
+int xcorr_pipe_dump(xcorr_pipe *p, void *d_out, int64_t *n_integrated, uint64_t *n_gaps)
+{
+    if (!p || !d_out)
+        return api_error(XCORR_E_INVAL, "pipe or d_out is NULL");
+    const int rc = flush_held(p, d_out, true, n_integrated, n_gaps);
+    if (rc == XCORR_OK) {
+        p->since_dump = 0;
+        ++p->dumps;
+    }
+    return rc;
 }
 
 int xcorr_pipe_set_fuse(xcorr_pipe *p, int fuse)

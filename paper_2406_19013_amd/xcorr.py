@@ -84,6 +84,31 @@ class PipeStats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+EV_BLOCK, EV_GAP, EV_DUMP = 1, 2, 3
+
+
+class Event(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32),
+        ("n_blocks", ctypes.c_int32),
+        ("n_missing", ctypes.c_int32),
+        ("valid", ctypes.c_int32),
+        ("seq", ctypes.c_uint64),
+        ("integration", ctypes.c_int64),
+        ("block", ctypes.c_void_p),
+    ]
+
+
+class ReorderStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("received", "released", "missing", "late", "duplicate",
+                                              "before_origin", "held", "integrations",
+                                              "invalid_integrations", "empty_integrations")] + [
+        ("next_seq", ctypes.c_uint64)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 _lock = threading.Lock()
 _lib = None
 
@@ -125,6 +150,14 @@ def load(path: str | None = None):
             "xcorr_ingest_blocks": [vp, ctypes.POINTER(vp), ctypes.c_int, i64, u64, vp],
             "xcorr_ingest_dump": [vp, vp, i64, u64, vp, ctypes.POINTER(i64), ctypes.POINTER(u64), vp],
             "xcorr_pipe_destroy": [vp],
+            "xcorr_pipe_dump": [vp, vp, ctypes.POINTER(i64), ctypes.POINTER(u64)],
+            "xcorr_reorder_init": [i64, ctypes.c_int32, ctypes.c_int32, u64, ctypes.POINTER(vp)],
+            "xcorr_reorder_push": [vp, u64, vp, ctypes.POINTER(Event), ctypes.c_int32,
+                                   ctypes.POINTER(ctypes.c_int32)],
+            "xcorr_reorder_flush": [vp, ctypes.c_int32, ctypes.POINTER(Event), ctypes.c_int32,
+                                    ctypes.POINTER(ctypes.c_int32)],
+            "xcorr_reorder_stats": [vp, ctypes.POINTER(ReorderStats)],
+            "xcorr_reorder_destroy": [vp],
             "xcorr_admit": [cfgp, ctypes.c_int, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_int32), sz,
                             ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(sz)],
         }
@@ -132,6 +165,8 @@ def load(path: str | None = None):
             fn = getattr(lib, name)
             fn.argtypes = args
             fn.restype = ctypes.c_int
+        lib.xcorr_reorder_max_events.argtypes = [ctypes.c_int32]
+        lib.xcorr_reorder_max_events.restype = ctypes.c_int32
         lib.xcorr_strerror.argtypes = [ctypes.c_int]
         lib.xcorr_strerror.restype = ctypes.c_char_p
         lib.xcorr_last_error.argtypes = []
@@ -331,6 +366,49 @@ def xcorr_pipe_destroy(pipe):
     _check(load().xcorr_pipe_destroy(pipe), "xcorr_pipe_destroy")
 
 
+def xcorr_pipe_dump(pipe, out):
+    """End the integration now: (samples integrated, sequence gaps)."""
+    n, g = ctypes.c_int64(), ctypes.c_uint64()
+    _check(load().xcorr_pipe_dump(pipe, ctypes.c_void_p(out.data_ptr()), ctypes.byref(n), ctypes.byref(g)),
+           "xcorr_pipe_dump")
+    return n.value, g.value
+
+
+def xcorr_reorder_max_events(window: int) -> int:
+    return int(load().xcorr_reorder_max_events(int(window)))
+
+
+def xcorr_reorder_init(blocks_per_dump: int, window: int, max_missing: int, seq_origin: int):
+    r = ctypes.c_void_p()
+    _check(load().xcorr_reorder_init(int(blocks_per_dump), int(window), int(max_missing), int(seq_origin),
+                                     ctypes.byref(r)), "xcorr_reorder_init")
+    return r
+
+
+def xcorr_reorder_push(r, seq: int, handle: int, events, max_events: int) -> int:
+    n = ctypes.c_int32()
+    _check(load().xcorr_reorder_push(r, int(seq), ctypes.c_void_p(handle), events, int(max_events),
+                                     ctypes.byref(n)), "xcorr_reorder_push")
+    return n.value
+
+
+def xcorr_reorder_flush(r, to_boundary: bool, events, max_events: int) -> int:
+    n = ctypes.c_int32()
+    _check(load().xcorr_reorder_flush(r, int(to_boundary), events, int(max_events), ctypes.byref(n)),
+           "xcorr_reorder_flush")
+    return n.value
+
+
+def xcorr_reorder_stats(r) -> dict:
+    st = ReorderStats()
+    _check(load().xcorr_reorder_stats(r, ctypes.byref(st)), "xcorr_reorder_stats")
+    return st.as_dict()
+
+
+def xcorr_reorder_destroy(r):
+    _check(load().xcorr_reorder_destroy(r), "xcorr_reorder_destroy")
+
+
 def xcorr_admit(cfgs, block_samples, n_slots, budget_bytes: int):
     """(admitted flags, bytes used) for configs walked in order against a budget."""
     n = len(cfgs)
@@ -496,6 +574,14 @@ class Pipe:
     def set_fuse(self, fuse: int):
         xcorr_pipe_set_fuse(self.pipe, fuse)
 
+    def dump(self, out):
+        """End the integration now (dump_every = 0 pipes dump only here):
+        (samples integrated, sequence gaps)."""
+        import torch
+        self.compute_stream.wait_stream(torch.cuda.current_stream())
+        out.record_stream(self.compute_stream)
+        return xcorr_pipe_dump(self.pipe, out)
+
     def drain(self):
         xcorr_pipe_drain(self.pipe)
 
@@ -509,6 +595,67 @@ class Pipe:
         if self.pipe:
             xcorr_pipe_destroy(self.pipe)
             self.pipe = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Reorder:
+    """Block reassembly by sequence number (pure host): push arriving blocks
+    in any order, get back what each arrival settles, in sequence order, as
+    dicts {"kind": "block" | "gap" | "dump", "seq", "integration", ...}; a
+    block event carries the object that was pushed."""
+
+    _KIND = {EV_BLOCK: "block", EV_GAP: "gap", EV_DUMP: "dump"}
+
+    def __init__(self, blocks_per_dump: int, window: int, max_missing: int = 0, seq_origin: int = 0):
+        self.r = xcorr_reorder_init(blocks_per_dump, window, max_missing, seq_origin)
+        self.max_events = xcorr_reorder_max_events(window)
+        self._events = (Event * self.max_events)()
+        self._held = {}
+        self._next_handle = 1
+        self._dropped = 0
+
+    def _convert(self, n: int) -> list:
+        out = []
+        for e in self._events[:n]:
+            d = {"kind": self._KIND[e.kind], "seq": e.seq, "integration": e.integration}
+            if e.kind == EV_BLOCK:
+                d["block"] = self._held.pop(e.block)
+            elif e.kind == EV_GAP:
+                d["n"] = e.n_blocks
+            else:
+                d.update(n_blocks=e.n_blocks, n_missing=e.n_missing, valid=bool(e.valid))
+            out.append(d)
+        return out
+
+    def push(self, seq: int, block=None) -> list:
+        h = self._next_handle
+        self._next_handle += 1
+        self._held[h] = block
+        n = xcorr_reorder_push(self.r, seq, h, self._events, self.max_events)
+        ev = self._convert(n)
+        # a dropped block (late, duplicate, before the origin) is not held
+        st = self.stats()
+        dropped = st["late"] + st["duplicate"] + st["before_origin"]
+        if dropped > self._dropped:
+            self._dropped = dropped
+            self._held.pop(h, None)
+        return ev
+
+    def flush(self, to_boundary: bool = True) -> list:
+        return self._convert(xcorr_reorder_flush(self.r, to_boundary, self._events, self.max_events))
+
+    def stats(self) -> dict:
+        return xcorr_reorder_stats(self.r)
+
+    def close(self):
+        if self.r:
+            xcorr_reorder_destroy(self.r)
+            self.r = None
 
     def __del__(self):
         try:
