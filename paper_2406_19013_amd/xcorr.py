@@ -636,7 +636,11 @@ class Reorder:
         h = self._next_handle
         self._next_handle += 1
         self._held[h] = block
-        n = xcorr_reorder_push(self.r, seq, h, self._events, self.max_events)
+        try:
+            n = xcorr_reorder_push(self.r, seq, h, self._events, self.max_events)
+        except XcorrError:
+            self._held.pop(h, None)
+            raise
         ev = self._convert(n)
         # a dropped block (late, duplicate, before the origin) is not held
         st = self.stats()
