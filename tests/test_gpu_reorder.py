@@ -66,3 +66,28 @@ def test_reassembled_stream_matches_oracle(fuse):
     p.close()
     r.close()
     c.close()
+
+
+def test_explicit_dump_restarts_the_count():
+    """An explicit dump ends the integration and restarts the count of
+    dump_every: blocks 0-1 (explicit), then 2-4 (automatic after three)."""
+    N, F, B = 32, 2, 64
+    print(f"explicit dump N={N} F={F} B={B}", flush=True)
+    blocks = [synth.uniform_volts4(N, F, B, seed=(4102, k)) for k in range(6)]
+    c = X.Correlator(N, F, 4, X.PATH_I8_MFMA)
+    p = X.Pipe(c, B, 3, host_blocks=False)
+    outs = [torch.empty((F, N * (N + 1) // 2, 2), dtype=torch.int32, device="cuda") for _ in range(2)]
+    p.push(blocks[0].cuda(), seq=0)
+    p.push(blocks[1].cuda(), seq=1)
+    n, gaps = p.dump(outs[0])
+    assert (n, gaps) == (2 * B, 0)
+    dumped = [p.push(blocks[k].cuda(), out=outs[1], seq=k) for k in (2, 3, 4)]
+    assert dumped == [False, False, True]
+    p.drain()
+    torch.cuda.synchronize()
+    for o, ks in ((outs[0], (0, 1)), (outs[1], (2, 3, 4))):
+        v = torch.cat([blocks[k] for k in ks])
+        want = oracle.to_int32(oracle.xcorr(v.numpy(), 4, v.shape[0], F, N))
+        assert np.array_equal(o.cpu().numpy(), want), ks
+    p.close()
+    c.close()
