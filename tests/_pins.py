@@ -228,6 +228,37 @@ def pin_consistency(lib, N=9, F=3, T=45):
             assert oracle.xcorr_pair(v, bits, T, F, N, f, i, j, lib=lib) == tuple(a[f, oracle.pair_index(i, j)])
 
 
+def pin_double_beyond_2_pow_24(lib, T=1500):
+    """The double oracle is the FP64 reference of the half-precision path,
+    whose partial sums pass 2^24 in its stress case: there every integer sum
+    must still come out exact (below 2^53).  Closed form: every input carries
+    (127, 126) and input 3 carries (-126, 127) = i * (127, 126), so the autos
+    are (127^2 + 126^2) T = 32005 T (odd per sample, so a single-precision
+    accumulator would round past 2^24), pairs (1, 0) and (2, 0) equal the auto,
+    and V_30 = i * 32005 T; random 8-bit inputs then agree with the int64
+    oracle at the same magnitude."""
+    N, F = 4, 2
+    re = torch.full((T, F, N), 127, dtype=torch.int64)
+    im = torch.full((T, F, N), 126, dtype=torch.int64)
+    re[:, :, 3], im[:, :, 3] = -126, 127
+    v = synth.pack8(re, im).numpy()
+    d = oracle.xcorr_f64(v, 8, T, F, N, lib=lib)
+    big = 32005 * T
+    assert big > 2 ** 24
+    for i in range(N):
+        p = oracle.pair_index(i, i)
+        assert np.all(d[:, p, 0] == big) and np.all(d[:, p, 1] == 0), "auto beyond 2^24 is not exact"
+    for i in (1, 2):
+        assert np.all(d[:, oracle.pair_index(i, 0), 0] == big) and np.all(d[:, oracle.pair_index(i, 0), 1] == 0)
+    p30 = oracle.pair_index(3, 0)
+    assert np.all(d[:, p30, 0] == 0) and np.all(d[:, p30, 1] == big), "quarter-turn pair beyond 2^24"
+    v8 = synth.uniform_volts8(N, F, T, seed=(82,), lo=100, hi=127).numpy()
+    a = oracle.xcorr(v8, 8, T, F, N, lib=lib)
+    d8 = oracle.xcorr_f64(v8, 8, T, F, N, lib=lib)
+    assert np.abs(a).max() > 2 ** 24
+    assert np.array_equal(a, d8.astype(np.int64)), "double oracle differs from int64 beyond 2^24"
+
+
 ALL_PINS = [
     pin_library_zherk,
     pin_reversal_hermitian,
@@ -239,4 +270,5 @@ ALL_PINS = [
     pin_overflow_edge,
     pin_distribution,
     pin_consistency,
+    pin_double_beyond_2_pow_24,
 ]

@@ -29,6 +29,7 @@ MUTANTS = [
     ("channel_stride_swapped", "uint8_t b = v[(t * F + f) * N + i];", "uint8_t b = v[(f * T + t) * N + i];"),
     ("int32_accumulator", "int64_t acc_re = 0, acc_im = 0;\n                for (int64_t t = 0; t < T; ++t) {\n                    int64_t ri",
      "int32_t acc_re = 0, acc_im = 0;\n                for (int64_t t = 0; t < T; ++t) {\n                    int64_t ri"),
+    ("float_accumulator_in_double_loop", "double acc_re = 0.0, acc_im = 0.0;", "float acc_re = 0.0f, acc_im = 0.0f;"),
 ]
 
 
