@@ -93,6 +93,7 @@ typedef struct {
     uint64_t seq_gaps_total;
     int32_t tile;               /* diagonal block size in use (MFMA paths) */
     int32_t regions_per_chan;   /* work-groups per channel in one ingest */
+    int32_t tile_from_cache;    /* 1: the tile came from a tune-cache line */
 } xcorr_stats_t;
 
 /*
@@ -109,7 +110,10 @@ typedef struct {
 int xcorr_query(const xcorr_config *cfg, size_t *workspace_bytes, size_t *out_bytes, int64_t *t_max);
 
 /*
- * Create a context on the current HIP device.  d_workspace (>= workspace_bytes
+ * Create a context on the current HIP device: the state of one correlator
+ * instance, i.e. the accumulators the GPU thread of a hashpipe instance
+ * integrates into between two hand-offs to its output thread (Section 2.3
+ * "X-engine").  d_workspace (>= workspace_bytes
  * from xcorr_query) is borrowed until xcorr_destroy; its contents need no
  * initialisation.  Errors: as xcorr_query, XCORR_E_NOMEM if ws_bytes is too
  * small or d_workspace is NULL, XCORR_E_DEVICE if the device is not gfx950,
@@ -118,6 +122,8 @@ int xcorr_query(const xcorr_config *cfg, size_t *workspace_bytes, size_t *out_by
 int xcorr_init(const xcorr_config *cfg, void *d_workspace, size_t ws_bytes, xcorr_ctx **out);
 
 /*
+ * The conjugate multiply-accumulate of Section 2.3 "X-engine" on one block of
+ * channelised voltages (Eq. 2 of Section 3.2 defines the product).
  * Correlate n_samples >= 1 time samples, d_volts = [n_samples][F][N] in the
  * configured format, and add them to the integration (the first ingest after
  * a dump overwrites the accumulators).  d_volts stays caller-owned and must
@@ -144,6 +150,8 @@ int xcorr_ingest_blocks(xcorr_ctx *ctx, const void *const *d_blocks, int n_block
                         uint64_t first_seq, void *stream);
 
 /*
+ * End an integration (Section 2.4 "Data storage": about 4 s per integration;
+ * Section 2.3: the output thread takes the GPU thread's result buffer).
  * Write the integration to d_out ([F][P][2], out_bytes from xcorr_query) and
  * start a new one.  A dump of an empty integration writes zeros.
  * n_integrated / n_gaps (may be NULL) receive the samples and the counted
@@ -152,7 +160,8 @@ int xcorr_ingest_blocks(xcorr_ctx *ctx, const void *const *d_blocks, int n_block
 int xcorr_dump(xcorr_ctx *ctx, void *d_out, int64_t *n_integrated, uint64_t *n_gaps, void *stream);
 
 /*
- * The last ingest of an integration and its dump in one call: as
+ * The last block of an integration and its hand-off (Sections 2.3 and 2.4),
+ * in one call: as
  * xcorr_ingest(ctx, d_volts, n_samples, seq) followed by xcorr_dump(ctx,
  * d_out, ...), with the same results.  On the 4+4-bit int8-MFMA path the
  * final launch adds the running sums to its own and writes the visibilities
@@ -162,6 +171,11 @@ int xcorr_dump(xcorr_ctx *ctx, void *d_out, int64_t *n_integrated, uint64_t *n_g
 int xcorr_ingest_dump(xcorr_ctx *ctx, const void *d_volts, int64_t n_samples, uint64_t seq, void *d_out,
                       int64_t *n_integrated, uint64_t *n_gaps, void *stream);
 
+/*
+ * Counters of a context (the status values a hashpipe thread publishes each
+ * cycle, Section 2.3) and its destruction (the workspace is released to the
+ * caller).  Errors: XCORR_E_INVAL for NULL arguments.
+ */
 int xcorr_stats(const xcorr_ctx *ctx, xcorr_stats_t *out);
 int xcorr_destroy(xcorr_ctx *ctx);
 
@@ -202,19 +216,33 @@ int xcorr_batch_tiles(const xcorr_batch *b, int32_t *tiles);
 int xcorr_batch_destroy(xcorr_batch *b);
 
 /*
- * Autotuner: times every supported tile of an MFMA-path config on a
- * synthetic block of 2048 samples (a fixed hash pattern written into the
- * scratch) and returns the fastest in *best_tile; when $XCORR_TUNE_CACHE
- * names a file, the line "bits N F path tile" is appended to it, and
- * xcorr_init with tile = 0 then uses the last matching line.  The call
- * blocks until the timing runs on `stream` have finished.
- * xcorr_autotune_query gives the scratch size (accumulators + input block).
- * Errors: as xcorr_query, XCORR_E_INVAL for the plain path or a NULL
- * best_tile, XCORR_E_NOMEM for missing or short scratch, XCORR_E_HIP.
+ * Autotuner (the triangle-tile choice of the work split; the paper's X-engine
+ * runs a fixed tiling, Section 2.3).  xcorr_autotune times every supported
+ * tile of an MFMA-path config on the kernel a context of that config runs
+ * (xcorr_autotune_kernel names it), over a synthetic block of 2048 samples
+ * (a fixed hash pattern written into the scratch), and returns the fastest
+ * in *best_tile.  xcorr_autotune_batch does the same on the batched
+ * persistent kernel, with the config as its only array, over the tiles that
+ * kernel carries (2, 3, 4, and 6 when N <= 192).  When $XCORR_TUNE_CACHE
+ * names a file, the line "bits N F path tile kernel" is appended to it;
+ * xcorr_init with tile = 0 (and xcorr_batch_init, for each member) then uses
+ * the last line of that config whose kernel is the one it will run; lines
+ * timed on another kernel are ignored.  xcorr_plan_tile (pure host) reports
+ * the tile xcorr_init (batch = 0) or xcorr_batch_init (batch = 1) would use
+ * and whether it came from the cache.  The tuners block until their timing
+ * runs on `stream` have finished.  xcorr_autotune_query gives the scratch
+ * size (accumulators + input block + queue counters).
+ * Errors: as xcorr_query, XCORR_E_INVAL for the plain path, a NULL output,
+ * or (batch) a config that is not 4+4-bit int8 MFMA; XCORR_E_NOMEM for
+ * missing or short scratch; XCORR_E_HIP.
  */
 int xcorr_autotune_query(const xcorr_config *cfg, size_t *scratch_bytes);
 int xcorr_autotune(const xcorr_config *cfg, void *d_scratch, size_t scratch_bytes, void *stream,
                    int32_t *best_tile);
+int xcorr_autotune_batch(const xcorr_config *cfg, void *d_scratch, size_t scratch_bytes, void *stream,
+                         int32_t *best_tile);
+int xcorr_autotune_kernel(const xcorr_config *cfg, int32_t batch, char *name, size_t len);
+int xcorr_plan_tile(const xcorr_config *cfg, int32_t batch, int32_t *tile, int32_t *from_cache);
 /*
  * Streaming loop (the X-engine node's packet ring feeding the correlator,
  * which integrates and hands each integration to an output stage: Section
@@ -224,11 +252,18 @@ int xcorr_autotune(const xcorr_config *cfg, void *d_scratch, size_t scratch_byte
  * is reused once its previous ingest has finished), then ingested on
  * `compute_stream` after the copy; a device block (on_host = 0) is ingested
  * in place.  Every dump_every-th block the integration is dumped into d_out
- * (required on that push, *dumped = 1).  Each block's latency, from the start
- * of its transfer (host blocks) or of its ingest (device blocks) to the end
- * of its ingest (and dump), is taken from HIP events; xcorr_pipe_stats
- * reports nearest-rank p50 / p99 and the maximum over the reaped blocks
- * (xcorr_pipe_drain waits for every block in flight).  Calls are
+ * (required on that push, *dumped = 1).  Two latencies are kept.  The service
+ * time of each launch record (one block, or a held group), from the start of
+ * its transfer (host blocks) or of its ingest (device blocks) to the end of
+ * its ingest (and dump), comes from HIP events.  The block latency, per
+ * block, runs from the host clock at its xcorr_pipe_push call to the end of
+ * the ingest that holds it, so it includes queueing behind earlier blocks; a
+ * GPU event maps onto the host clock through an anchor event taken at init
+ * and at each xcorr_pipe_reset_latency (its uncertainty is reported).
+ * xcorr_pipe_stats reports nearest-rank p50 / p99 and the maximum of both
+ * over the reaped records (xcorr_pipe_drain waits for every block in
+ * flight) and `held`, the device blocks whose ingest is not enqueued yet
+ * (the newest `held` pushes).  Calls are
  * asynchronous except that at most max(8, 4 n_slots) blocks are in flight:
  * a push beyond that waits for the oldest.  The host block, d_out and device
  * blocks must stay valid until the streams pass them.
@@ -247,7 +282,11 @@ int xcorr_autotune(const xcorr_config *cfg, void *d_scratch, size_t scratch_byte
  */
 typedef struct {
     int64_t blocks, dumps, latencies;
-    double p50_ms, p99_ms, max_ms, mean_ms;
+    double p50_ms, p99_ms, max_ms, mean_ms;   /* service time per record */
+    int64_t held;                /* device blocks pushed but not yet ingested */
+    int64_t submit_latencies;    /* blocks with a submit-to-done latency */
+    double submit_p50_ms, submit_p99_ms, submit_max_ms;
+    double clock_anchor_err_ms;  /* uncertainty of the host-clock anchor */
 } xcorr_pipe_stats_t;
 
 int xcorr_pipe_query(const xcorr_ctx *ctx, int n_slots, int64_t block_samples, size_t *ring_bytes);

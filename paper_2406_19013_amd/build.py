@@ -1,8 +1,10 @@
 """Build libxcorr.so (HIP kernels + C ABI) for gfx950 with hipcc.
 
-    python -m paper_2406_19013_amd.build [--verbose]
+    python -m paper_2406_19013_amd.build [--verbose] [--changed]
 
-Every call compiles; the library is written next to this file.  The
+Every call compiles every unit (--changed: only units whose object is older
+than a source or header, for editing sessions); the library is written next
+to this file.  The
 compiler's per-kernel resource report (registers, scratch, occupancy, LDS) is
 written to _build/kernel_resources.txt; a kernel that spills registers to
 scratch is named on stderr.
@@ -86,20 +88,41 @@ def read_resources(path: str | None = None) -> dict:
     return res
 
 
-def build(verbose: bool = False, jobs: int | None = None) -> str:
+def _stale(obj: str, src: str) -> bool:
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    deps = [os.path.join(CSRC, src)] + [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".h")] + \
+        [os.path.join(INCLUDE, h) for h in os.listdir(INCLUDE) if h.endswith(".h")]
+    return any(os.path.getmtime(d) > t for d in deps)
+
+
+def build(verbose: bool = False, jobs: int | None = None, changed_only: bool = False) -> str:
     cc = hipcc()
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
     objs = [os.path.join(bdir, o) for _, _, o in UNITS]
     cmds = [[cc, *COMMON, *flags, "-Rpass-analysis=kernel-resource-usage", "-c",
              os.path.join(CSRC, src), "-o", obj]
-            for (src, flags, _), obj in zip(UNITS, objs)]
+            for (src, flags, _), obj in zip(UNITS, objs)
+            if not changed_only or _stale(obj, src)]
     jobs = jobs or min(len(cmds), max(1, min(16, os.cpu_count() or 1)))
-    with cf.ThreadPoolExecutor(jobs) as ex:
+    with cf.ThreadPoolExecutor(max(1, jobs)) as ex:
         reports = list(ex.map(lambda c: _run(c, verbose), cmds))
+    # per-unit resource reports, merged into one file
+    for c, kernels in zip(cmds, reports):
+        with open(c[-1] + ".res", "w") as fh:
+            for name, f in kernels:
+                fh.write(name + " " + " ".join(f"{k}={v}" for k, v in f.items()) + "\n")
     with open(os.path.join(bdir, RESOURCES), "w") as fh:
         fh.write("# kernel VGPRs AGPRs ScratchSize(bytes/lane) Occupancy(waves/SIMD) LDS(bytes)\n")
-        for kernels in reports:
+        for obj in objs:
+            kernels = []
+            if os.path.exists(obj + ".res"):
+                for line in open(obj + ".res"):
+                    parts = line.split()
+                    if parts:
+                        kernels.append((parts[0], dict(p.split("=", 1) for p in parts[1:])))
             for name, f in kernels:
                 fields = " ".join(f"{k}={f[k]}" for k in ("VGPRs", "AGPRs", "ScratchSize", "Occupancy", "LDS")
                                   if k in f)
@@ -114,4 +137,4 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="--verbose" in sys.argv))
+    print(build(verbose="--verbose" in sys.argv, changed_only="--changed" in sys.argv))

@@ -14,11 +14,18 @@
 #include <string>
 #include <vector>
 
+// Kernel family a 4+4-bit int8-MFMA context runs (the tuner times the same).
+enum class Kernel4 {
+    Fused,   // fused products: one Re and one Im accumulator per tile
+    Roles,   // one wave per real product ($XCORR_MFMA4_VARIANT=roles)
+};
+
 struct xcorr_ctx {
     xcorr_config cfg;
     xc::Plan plan;
     int kc;
-    bool per_role;   // 4+4-bit: per-role kernel instead of the fused-product one
+    Kernel4 k4;
+    int tile_from_cache;   // the tile came from a tune-cache line
     void *ws;
     size_t ws_bytes;
     int64_t t_max;
@@ -75,9 +82,34 @@ int default_tile(int N)
     return 4;
 }
 
-// Tune cache: a text file of "bits N F path tile" lines written by the
-// autotuner; the path named by $XCORR_TUNE_CACHE.
-int cached_tile(const xcorr_config &c)
+Kernel4 kernel4_from_env()
+{
+    const char *fv = std::getenv("XCORR_MFMA4_VARIANT");
+    return fv && std::strcmp(fv, "roles") == 0 ? Kernel4::Roles : Kernel4::Fused;
+}
+
+// Name of the kernel an ingest of this config launches (batch = 0) or that
+// the batched launch runs for it (batch = 1); the tuner times that kernel and
+// labels its tune-cache line with this name.
+const char *kernel_name(const xcorr_config &c, bool batch)
+{
+    if (c.path == XCORR_PATH_PLAIN)
+        return "xc_plain_kernel";
+    if (batch)
+        return "xc_batch4_kernel";
+    if (c.sample_bits == 8)
+        return c.path == XCORR_PATH_F16_MFMA ? "xc_mfma8_kernel_f16" : "xc_mfma8_kernel_i8";
+    return kernel4_from_env() == Kernel4::Roles ? "xc_mfma4_kernel" : "xc_mfma4f_kernel";
+}
+
+// Tiles the batched kernel carries for an array of N inputs.
+bool batch_tile_supported(int N, int D) { return (D >= 2 && D <= 4) || (D == 6 && N <= 192); }
+
+// Tune cache: a text file of "bits N F path tile kernel" lines written by the
+// autotuner; the path named by $XCORR_TUNE_CACHE.  The last line for this
+// config and for the kernel the caller will run wins; lines timed on another
+// kernel are ignored.
+int cached_tile(const xcorr_config &c, bool batch)
 {
     const char *path = std::getenv("XCORR_TUNE_CACHE");
     if (!path || !*path)
@@ -85,11 +117,19 @@ int cached_tile(const xcorr_config &c)
     FILE *fh = std::fopen(path, "r");
     if (!fh)
         return 0;
-    int bits, n, f, p, tile, found = 0;
-    while (std::fscanf(fh, "%d %d %d %d %d", &bits, &n, &f, &p, &tile) == 5)
+    const char *want = kernel_name(c, batch);
+    char line[256];
+    int found = 0;
+    while (std::fgets(line, sizeof line, fh)) {
+        int bits, n, f, p, tile;
+        char kern[96];
+        if (std::sscanf(line, "%d %d %d %d %d %95s", &bits, &n, &f, &p, &tile, kern) != 6)
+            continue;
         if (bits == c.sample_bits && n == c.n_inputs && f == c.n_chans && p == c.path &&
-            xc::plan_supported(n, tile))
+            std::strcmp(kern, want) == 0 &&
+            (batch ? batch_tile_supported(n, tile) : xc::plan_supported(n, tile)))
             found = tile;
+    }
     std::fclose(fh);
     return found;
 }
@@ -127,25 +167,35 @@ size_t acc_bytes(const xcorr_config &c)
     return (size_t)c.n_chans * (size_t)n_pairs(c.n_inputs) * 2 * 4;
 }
 
-// Region plan of a batch member: the context's own plan when its block size
-// is one the batched kernel carries (2, 3, 4, or 6 with N <= 192), else the
-// one of 2, 3, 4 with the fewest tiles (padding included), the larger on a tie.
-xc::Plan batch_plan(const xcorr_ctx *c)
+// Tile of a batch member when the tune cache has none for the batched
+// kernel: its own tile when the batched kernel carries it (2, 3, 4, or 6 with
+// N <= 192), else the one of 2, 3, 4 with the fewest tiles (padding
+// included), the larger on a tie.
+int batch_fallback_tile(int N, int own)
 {
-    const int D = c->plan.D;
-    if ((D >= 2 && D <= 4) || (D == 6 && c->cfg.n_inputs <= 192))
-        return c->plan;
-    xc::Plan best;
+    if (batch_tile_supported(N, own))
+        return own;
+    int best = 0;
     int64_t best_tiles = -1;
     for (int d = 2; d <= 4; ++d) {
-        const xc::Plan p = xc::make_plan(c->cfg.n_inputs, d);
+        const xc::Plan p = xc::make_plan(N, d);
         const int64_t tiles = (int64_t)p.nseg * d * (d + 1) / 2 + (int64_t)p.nseg * (p.nseg - 1) / 2 * d * d;
         if (best_tiles < 0 || tiles <= best_tiles) {
-            best = p;
+            best = d;
             best_tiles = tiles;
         }
     }
     return best;
+}
+
+// Region plan of a batch member: the tile tuned for the batched kernel
+// (tune cache), else the fallback above.
+xc::Plan batch_plan(const xcorr_ctx *c)
+{
+    int d = cached_tile(c->cfg, true);
+    if (!d)
+        d = batch_fallback_tile(c->cfg.n_inputs, c->plan.D);
+    return xc::make_plan(c->cfg.n_inputs, d);
 }
 
 int device_cus(int *cus)
@@ -232,17 +282,19 @@ int xcorr_init(const xcorr_config *cfg, void *d_workspace, size_t ws_bytes, xcor
     c->max_dump = cfg->max_samples_per_dump ? cfg->max_samples_per_dump : tm;
     c->kc = 64;
     if (cfg->path != XCORR_PATH_PLAIN) {
-        int tile = cfg->tile ? cfg->tile : cached_tile(*cfg);
+        int tile = cfg->tile;
+        if (!tile) {
+            tile = cached_tile(*cfg, false);
+            c->tile_from_cache = tile != 0;
+        }
         if (!tile)
             tile = default_tile(cfg->n_inputs);
         c->plan = xc::make_plan(cfg->n_inputs, tile);
-        // time rows staged per LDS chunk (64 or 128; 128 for D >= 4 only)
+        // time rows staged per LDS chunk of the per-role kernel (64 or 128; 128 for D >= 4 only)
         const char *v = std::getenv("XCORR_CHUNK");
         if (v && std::strcmp(v, "128") == 0 && c->plan.D >= 4 && cfg->sample_bits == 4)
             c->kc = 128;
-        // $XCORR_MFMA4_VARIANT=roles selects the per-role 4+4-bit kernel
-        const char *fv = std::getenv("XCORR_MFMA4_VARIANT");
-        c->per_role = fv && std::strcmp(fv, "roles") == 0;
+        c->k4 = kernel4_from_env();
     }
     c->ws = d_workspace;
     c->ws_bytes = ws_bytes;
@@ -274,7 +326,7 @@ int xcorr_ingest(xcorr_ctx *ctx, const void *d_volts, int64_t n_samples, uint64_
         hipError_t e;
         if (c.path == XCORR_PATH_PLAIN)
             e = xc::launch_plain(c.sample_bits, vp, tl, c.n_chans, c.n_inputs, acc, accumulate, s);
-        else if (c.sample_bits == 4 && !ctx->per_role)
+        else if (c.sample_bits == 4 && ctx->k4 == Kernel4::Fused)
             e = xc::launch_mfma4f(ctx->plan, vp, tl, c.n_chans, c.n_inputs, acc, accumulate, s);
         else if (c.sample_bits == 4)
             e = xc::launch_mfma4(ctx->plan, ctx->kc, vp, tl, c.n_chans, c.n_inputs, acc, accumulate, s);
@@ -301,7 +353,7 @@ int xcorr_ingest_dump(xcorr_ctx *ctx, const void *d_volts, int64_t n_samples, ui
     if ((uintptr_t)d_out % 16)
         return set_error(XCORR_E_INVAL, "d_out must be 16-byte aligned");
     const xcorr_config &c = ctx->cfg;
-    if (!(c.sample_bits == 4 && c.path == XCORR_PATH_I8_MFMA && !ctx->per_role)) {
+    if (!(c.sample_bits == 4 && c.path == XCORR_PATH_I8_MFMA && ctx->k4 == Kernel4::Fused)) {
         const int rc = xcorr_ingest(ctx, d_volts, n_samples, seq, stream);
         return rc ? rc : xcorr_dump(ctx, d_out, n_integrated, n_gaps, stream);
     }
@@ -348,7 +400,8 @@ int xcorr_ingest_blocks(xcorr_ctx *ctx, const void *const *d_blocks, int n_block
     if (block_samples > (ctx->max_dump - ctx->acc_samples) / n_blocks)
         return set_error(XCORR_E_OVERFLOW, "integration would exceed max_samples_per_dump");
     const xcorr_config &c = ctx->cfg;
-    bool fused = c.sample_bits == 4 && c.path == XCORR_PATH_I8_MFMA && !ctx->per_role && block_samples % 64 == 0 &&
+    bool fused = c.sample_bits == 4 && c.path == XCORR_PATH_I8_MFMA && ctx->k4 == Kernel4::Fused &&
+                 block_samples % 64 == 0 &&
                  block_samples <= xc::kMaxSamplesPerLaunch4 && c.n_inputs % 16 == 0 &&
                  64LL * c.n_chans * c.n_inputs < (1LL << 31) - 16;
     for (int b = 0; b < n_blocks && fused; ++b)
@@ -415,6 +468,7 @@ int xcorr_stats(const xcorr_ctx *ctx, xcorr_stats_t *out)
     out->seq_gaps_total = ctx->gaps_total;
     out->tile = ctx->plan.D;
     out->regions_per_chan = ctx->plan.regions;
+    out->tile_from_cache = ctx->tile_from_cache;
     return XCORR_OK;
 }
 
@@ -586,12 +640,102 @@ int xcorr_autotune_query(const xcorr_config *cfg, size_t *scratch_bytes)
         return set_error(XCORR_E_INVAL, "the plain path has no tile to tune");
     const size_t volts = (size_t)tune_samples() * cfg->n_chans * cfg->n_inputs * (cfg->sample_bits == 4 ? 1 : 2);
     if (scratch_bytes)
-        *scratch_bytes = round_up(acc_bytes(*cfg), 256) + round_up(volts, 256);
+        *scratch_bytes = round_up(acc_bytes(*cfg), 256) + round_up(volts, 256) + 256;
     return XCORR_OK;
 }
 
-int xcorr_autotune(const xcorr_config *cfg, void *d_scratch, size_t scratch_bytes, void *stream,
-                   int32_t *best_tile)
+int xcorr_autotune_kernel(const xcorr_config *cfg, int32_t batch, char *name, size_t len)
+{
+    const int rc = validate(cfg, nullptr);
+    if (rc)
+        return rc;
+    if (!name || len < 1)
+        return set_error(XCORR_E_INVAL, "name is NULL or empty");
+    if (batch && (cfg->sample_bits != 4 || cfg->path != XCORR_PATH_I8_MFMA))
+        return set_error(XCORR_E_INVAL, "the batched launch takes 4+4-bit int8-MFMA configs");
+    std::snprintf(name, len, "%s", kernel_name(*cfg, batch != 0));
+    return XCORR_OK;
+}
+
+int xcorr_plan_tile(const xcorr_config *cfg, int32_t batch, int32_t *tile, int32_t *from_cache)
+{
+    const int rc = validate(cfg, nullptr);
+    if (rc)
+        return rc;
+    if (!tile)
+        return set_error(XCORR_E_INVAL, "tile is NULL");
+    if (cfg->path == XCORR_PATH_PLAIN)
+        return set_error(XCORR_E_INVAL, "the plain path has no tile");
+    if (batch && (cfg->sample_bits != 4 || cfg->path != XCORR_PATH_I8_MFMA))
+        return set_error(XCORR_E_INVAL, "the batched launch takes 4+4-bit int8-MFMA configs");
+    int cached = 0;
+    int d = 0;
+    if (batch) {
+        d = cached_tile(*cfg, true);
+        cached = d != 0;
+        if (!d) {
+            const int own = cfg->tile ? cfg->tile : cached_tile(*cfg, false);
+            d = batch_fallback_tile(cfg->n_inputs, own ? own : default_tile(cfg->n_inputs));
+        }
+    } else {
+        d = cfg->tile;
+        if (!d) {
+            d = cached_tile(*cfg, false);
+            cached = d != 0;
+        }
+        if (!d)
+            d = default_tile(cfg->n_inputs);
+    }
+    *tile = d;
+    if (from_cache)
+        *from_cache = cached;
+    return XCORR_OK;
+}
+
+}  // extern "C"
+
+// Time `run` (a launch of the kernel under test) with HIP events: one
+// warm-up launch, then kReps launches; *ms is their total.
+template <class Run>
+static hipError_t time_launches(Run &&run, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, float *ms)
+{
+    constexpr int kReps = 5;
+    hipError_t e = run(0);
+    if (e == hipSuccess)
+        e = hipEventRecord(ev0, s);
+    for (int r = 0; r < kReps && e == hipSuccess; ++r)
+        e = run(1);
+    if (e == hipSuccess)
+        e = hipEventRecord(ev1, s);
+    if (e == hipSuccess)
+        e = hipEventSynchronize(ev1);
+    if (e == hipSuccess)
+        e = hipEventElapsedTime(ms, ev0, ev1);
+    return e;
+}
+
+extern "C" {
+
+static int append_tune_line(const xcorr_config &c, int tile, bool batch)
+{
+    const char *path = std::getenv("XCORR_TUNE_CACHE");
+    if (!path || !*path)
+        return XCORR_OK;
+    FILE *fh = std::fopen(path, "a");
+    if (!fh)
+        return set_error(XCORR_E_INVAL, std::string("cannot append to the tune cache ") + path);
+    std::fprintf(fh, "%d %d %d %d %d %s\n", c.sample_bits, c.n_inputs, c.n_chans, c.path, tile,
+                 kernel_name(c, batch));
+    std::fclose(fh);
+    return XCORR_OK;
+}
+
+// Shared body of the two tuners: candidate tiles of the config, each timed
+// on the kernel the caller will run (batch = 0: the ingest kernel of a
+// context; batch = 1: the batched persistent kernel with this config as its
+// only array).
+static int autotune_impl(const xcorr_config *cfg, void *d_scratch, size_t scratch_bytes, void *stream,
+                         int32_t *best_tile, bool batch)
 {
     size_t need = 0;
     int rc = xcorr_autotune_query(cfg, &need);
@@ -599,6 +743,8 @@ int xcorr_autotune(const xcorr_config *cfg, void *d_scratch, size_t scratch_byte
         return rc;
     if (!best_tile)
         return set_error(XCORR_E_INVAL, "best_tile is NULL");
+    if (batch && (cfg->sample_bits != 4 || cfg->path != XCORR_PATH_I8_MFMA))
+        return set_error(XCORR_E_INVAL, "the batched launch takes 4+4-bit int8-MFMA configs");
     if (!d_scratch || scratch_bytes < need)
         return set_error(XCORR_E_NOMEM, "scratch missing or smaller than xcorr_autotune_query's size");
     if ((uintptr_t)d_scratch % 256)
@@ -610,9 +756,15 @@ int xcorr_autotune(const xcorr_config *cfg, void *d_scratch, size_t scratch_byte
     uint8_t *volts = base + round_up(acc_bytes(c), 256);
     const int64_t T = tune_samples();
     const int64_t vbytes = T * c.n_chans * c.n_inputs * (c.sample_bits == 4 ? 1 : 2);
+    int *queue = reinterpret_cast<int *>(volts + round_up(vbytes, 256));
+    int cus = 0;
+    if (batch && (rc = device_cus(&cus)) != XCORR_OK)
+        return rc;
     hipError_t e = xc::launch_fill_pattern(volts, vbytes, c.sample_bits == 8, s);
+    if (e == hipSuccess && batch)
+        e = xc::launch_fill_zero(queue, xc::kBatchQueueInts, s);
     if (e != hipSuccess)
-        return hip_fail(e, "autotune input fill");
+        return hip_fail(e, "autotune set-up");
     hipEvent_t ev[2];
     if ((e = hipEventCreate(&ev[0])) != hipSuccess)
         return hip_fail(e, "hipEventCreate");
@@ -620,32 +772,45 @@ int xcorr_autotune(const xcorr_config *cfg, void *d_scratch, size_t scratch_byte
         (void)hipEventDestroy(ev[0]);
         return hip_fail(e, "hipEventCreate");
     }
+    const Kernel4 k4 = kernel4_from_env();
     int best = 0;
     float best_ms = 0.f;
     for (int d = 1; d <= 6 && e == hipSuccess; ++d) {
-        if (!xc::plan_supported(c.n_inputs, d))
+        if (batch ? !batch_tile_supported(c.n_inputs, d) : !xc::plan_supported(c.n_inputs, d))
             continue;
         const xc::Plan pl = xc::make_plan(c.n_inputs, d);
-        auto run = [&](int accumulate) {
-            return c.sample_bits == 4
-                       ? xc::launch_mfma4(pl, 64, volts, T, c.n_chans, c.n_inputs, static_cast<int2 *>(acc),
-                                          accumulate, s)
-                       : xc::launch_mfma8(pl, c.path == XCORR_PATH_F16_MFMA, volts, T, c.n_chans, c.n_inputs,
-                                          acc, accumulate, s);
+        auto run = [&](int accumulate) -> hipError_t {
+            if (batch) {
+                xc::BatchArgs args{};
+                args.n = 1;
+                xc::BatchArray &A = args.a[0];
+                A.volts = volts;
+                A.acc = static_cast<int2 *>(acc);
+                A.T = T;
+                A.F = c.n_chans;
+                A.N = c.n_inputs;
+                A.D = pl.D;
+                A.nseg = pl.nseg;
+                A.regions = pl.regions;
+                A.accumulate = accumulate;
+                A.item_begin = 0;
+                const int64_t items = (int64_t)c.n_chans * pl.regions;
+                if (items > (1LL << 30))
+                    return hipErrorInvalidValue;
+                args.total = (int)items;
+                const int vec = c.n_inputs % 16 == 0 && 64LL * c.n_chans * c.n_inputs < (1LL << 31) - 16;
+                return xc::launch_batch4(args, queue, vec, (int)std::min<int64_t>(cus, items), s);
+            }
+            if (c.sample_bits == 8)
+                return xc::launch_mfma8(pl, c.path == XCORR_PATH_F16_MFMA, volts, T, c.n_chans, c.n_inputs, acc,
+                                        accumulate, s);
+            if (k4 == Kernel4::Roles)
+                return xc::launch_mfma4(pl, 64, volts, T, c.n_chans, c.n_inputs, static_cast<int2 *>(acc),
+                                        accumulate, s);
+            return xc::launch_mfma4f(pl, volts, T, c.n_chans, c.n_inputs, static_cast<int2 *>(acc), accumulate, s);
         };
-        constexpr int kReps = 5;
-        e = run(0);   // warm-up
-        if (e == hipSuccess)
-            e = hipEventRecord(ev[0], s);
-        for (int r = 0; r < kReps && e == hipSuccess; ++r)
-            e = run(1);
-        if (e == hipSuccess)
-            e = hipEventRecord(ev[1], s);
-        if (e == hipSuccess)
-            e = hipEventSynchronize(ev[1]);
         float ms = 0.f;
-        if (e == hipSuccess)
-            e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+        e = time_launches(run, s, ev[0], ev[1], &ms);
         if (e == hipSuccess && (best == 0 || ms < best_ms)) {
             best = d;
             best_ms = ms;
@@ -656,15 +821,19 @@ int xcorr_autotune(const xcorr_config *cfg, void *d_scratch, size_t scratch_byte
     if (e != hipSuccess)
         return hip_fail(e, "autotune timing");
     *best_tile = best;
-    const char *path = std::getenv("XCORR_TUNE_CACHE");
-    if (path && *path) {
-        FILE *fh = std::fopen(path, "a");
-        if (!fh)
-            return set_error(XCORR_E_INVAL, std::string("cannot append to the tune cache ") + path);
-        std::fprintf(fh, "%d %d %d %d %d\n", c.sample_bits, c.n_inputs, c.n_chans, c.path, best);
-        std::fclose(fh);
-    }
-    return XCORR_OK;
+    return append_tune_line(c, best, batch);
+}
+
+int xcorr_autotune(const xcorr_config *cfg, void *d_scratch, size_t scratch_bytes, void *stream,
+                   int32_t *best_tile)
+{
+    return autotune_impl(cfg, d_scratch, scratch_bytes, stream, best_tile, false);
+}
+
+int xcorr_autotune_batch(const xcorr_config *cfg, void *d_scratch, size_t scratch_bytes, void *stream,
+                         int32_t *best_tile)
+{
+    return autotune_impl(cfg, d_scratch, scratch_bytes, stream, best_tile, true);
 }
 
 const char *xcorr_strerror(int code)

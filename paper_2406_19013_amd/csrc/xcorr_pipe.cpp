@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <deque>
 #include <new>
@@ -28,9 +29,19 @@ int hip_err(hipError_t e, const char *what)
     return api_error(XCORR_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// One latency record: a launch group (one block, or up to 8 held device
+// blocks ingested together) between two events on the compute stream, plus
+// the host clock at which each of its blocks was submitted.
 struct Record {
     hipEvent_t begin, end;
+    int nblk;
+    double submit_s[xc::kMaxFusedBlocks];
 };
+
+double host_now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
 
 }  // namespace
 
@@ -46,12 +57,20 @@ struct xcorr_pipe {
     std::vector<bool> slot_used;
     std::deque<Record> pending;                 // latency records in flight
     std::vector<Record> spare;
-    std::vector<float> lat_ms;
+    std::vector<float> lat_ms;         // service time per record
+    std::vector<float> submit_ms;      // host submit -> end of ingest, per block
     int64_t blocks = 0, dumps = 0, since_dump = 0, host_blocks = 0;
     size_t max_pending = 0;
     int fuse = 1;                      // device blocks ingested per group
     std::vector<const void *> held;    // device blocks pushed, not yet ingested
+    std::vector<double> held_submit;   // their host submit times
     uint64_t held_seq0 = 0;
+    // clock anchor: an event on the idle compute stream and the host time at
+    // which it ran (midpoint of record and synchronise), so that a GPU event
+    // maps onto the host clock as anchor_s + elapsed(anchor, event)
+    hipEvent_t anchor = nullptr;
+    double anchor_s = 0.0, anchor_err_s = 0.0;
+    bool have_anchor = false;
 };
 
 namespace {
@@ -72,25 +91,58 @@ void destroy_events(xcorr_pipe *p)
         (void)hipEventDestroy(r.begin);
         (void)hipEventDestroy(r.end);
     }
+    if (p->anchor)
+        (void)hipEventDestroy(p->anchor);
+    p->anchor = nullptr;
+    p->have_anchor = false;
     p->copied.clear();
     p->consumed.clear();
     p->pending.clear();
     p->spare.clear();
 }
 
-// Wait for the oldest latency record and keep its duration.
+// Set the clock anchor (the compute stream must be idle: after a drain).
+int set_anchor(xcorr_pipe *p)
+{
+    hipError_t e = hipSuccess;
+    if (!p->anchor)
+        e = hipEventCreate(&p->anchor);
+    const double a = host_now_s();
+    if (e == hipSuccess)
+        e = hipEventRecord(p->anchor, p->compute);
+    if (e == hipSuccess)
+        e = hipEventSynchronize(p->anchor);
+    const double b = host_now_s();
+    if (e != hipSuccess)
+        return hip_err(e, "clock anchor event");
+    p->anchor_s = 0.5 * (a + b);
+    p->anchor_err_s = 0.5 * (b - a);
+    p->have_anchor = true;
+    return XCORR_OK;
+}
+
+// Wait for the oldest latency record and keep its durations: the service
+// time of the record and, per block, the time from the host submit to the
+// end of its ingest.
 int reap_one(xcorr_pipe *p)
 {
     Record r = p->pending.front();
     p->pending.pop_front();
     hipError_t e = hipEventSynchronize(r.end);
-    float ms = 0.f;
+    float ms = 0.f, since_anchor = 0.f;
     if (e == hipSuccess)
         e = hipEventElapsedTime(&ms, r.begin, r.end);
+    if (e == hipSuccess && p->have_anchor)
+        e = hipEventElapsedTime(&since_anchor, p->anchor, r.end);
     p->spare.push_back(r);
     if (e != hipSuccess)
         return hip_err(e, "latency event");
     p->lat_ms.push_back(ms);
+    if (p->have_anchor) {
+        const double done_s = p->anchor_s + 1e-3 * since_anchor;
+        for (int k = 0; k < r.nblk; ++k)
+            p->submit_ms.push_back((float)std::max(0.0, 1e3 * (done_s - r.submit_s[k])));
+    }
     return XCORR_OK;
 }
 
@@ -133,6 +185,9 @@ int flush_held(xcorr_pipe *p, void *d_out, bool dump, int64_t *n_integrated = nu
     int rc = get_record(p, &r);
     if (rc)
         return rc;
+    r.nblk = (int)p->held.size();
+    for (int k = 0; k < r.nblk; ++k)
+        r.submit_s[k] = p->held_submit[k];
     hipError_t e = hipEventRecord(r.begin, p->compute);
     if (e != hipSuccess) {
         p->spare.push_back(r);
@@ -142,6 +197,7 @@ int flush_held(xcorr_pipe *p, void *d_out, bool dump, int64_t *n_integrated = nu
         rc = xcorr_ingest_blocks(p->ctx, p->held.data(), (int)p->held.size(), p->block_samples, p->held_seq0,
                                  p->compute);
         p->held.clear();
+        p->held_submit.clear();
     }
     if (rc == XCORR_OK && dump)
         rc = xcorr_dump(p->ctx, d_out, n_integrated, n_gaps, p->compute);
@@ -211,12 +267,19 @@ int xcorr_pipe_init(xcorr_ctx *ctx, int n_slots, int64_t block_samples, int64_t 
             return hip_err(e, "hipEventCreate");
         }
     }
+    rc = set_anchor(p);
+    if (rc) {
+        destroy_events(p);
+        delete p;
+        return rc;
+    }
     *out = p;
     return XCORR_OK;
 }
 
 int xcorr_pipe_push(xcorr_pipe *p, const void *block, int on_host, uint64_t seq, void *d_out, int *dumped)
 {
+    const double submit = host_now_s();
     if (!p || !block)
         return api_error(XCORR_E_INVAL, "pipe or block is NULL");
     if (on_host && !p->ring)
@@ -234,6 +297,7 @@ int xcorr_pipe_push(xcorr_pipe *p, const void *block, int on_host, uint64_t seq,
         if (p->held.empty())
             p->held_seq0 = seq;
         p->held.push_back(block);
+        p->held_submit.push_back(submit);
         ++p->blocks;
         ++p->since_dump;
         int rc = XCORR_OK;
@@ -259,6 +323,8 @@ int xcorr_pipe_push(xcorr_pipe *p, const void *block, int on_host, uint64_t seq,
     int rc = get_record(p, &r);
     if (rc)
         return rc;
+    r.nblk = 1;
+    r.submit_s[0] = submit;
     hipError_t e = hipSuccess;
     const void *src = block;
     if (on_host) {
@@ -370,23 +436,31 @@ int xcorr_pipe_stats(const xcorr_pipe *p, xcorr_pipe_stats_t *out)
     out->blocks = p->blocks;
     out->dumps = p->dumps;
     out->latencies = (int64_t)p->lat_ms.size();
-    out->p50_ms = out->p99_ms = out->max_ms = out->mean_ms = 0.0;
-    if (!p->lat_ms.empty()) {
-        std::vector<float> v(p->lat_ms);
+    out->held = (int64_t)p->held.size();
+    // nearest-rank percentiles, maximum and mean of a sample
+    auto summarise = [](const std::vector<float> &lat, double *p50, double *p99, double *mx, double *mean) {
+        *p50 = *p99 = *mx = *mean = 0.0;
+        if (lat.empty())
+            return;
+        std::vector<float> v(lat);
         std::sort(v.begin(), v.end());
-        // nearest-rank percentiles
         auto rank = [&](double q) {
             const size_t k = (size_t)std::ceil(q * v.size());
             return (double)v[std::min(v.size(), std::max<size_t>(k, 1)) - 1];
         };
-        out->p50_ms = rank(0.50);
-        out->p99_ms = rank(0.99);
-        out->max_ms = v.back();
+        *p50 = rank(0.50);
+        *p99 = rank(0.99);
+        *mx = v.back();
         double s = 0;
         for (float x : v)
             s += x;
-        out->mean_ms = s / v.size();
-    }
+        *mean = s / v.size();
+    };
+    summarise(p->lat_ms, &out->p50_ms, &out->p99_ms, &out->max_ms, &out->mean_ms);
+    double unused_mean = 0.0;
+    out->submit_latencies = (int64_t)p->submit_ms.size();
+    summarise(p->submit_ms, &out->submit_p50_ms, &out->submit_p99_ms, &out->submit_max_ms, &unused_mean);
+    out->clock_anchor_err_ms = 1e3 * p->anchor_err_s;
     return XCORR_OK;
 }
 
@@ -394,8 +468,11 @@ int xcorr_pipe_reset_latency(xcorr_pipe *p)
 {
     if (!p)
         return api_error(XCORR_E_INVAL, "pipe is NULL");
-    const int rc = xcorr_pipe_drain(p);
+    int rc = xcorr_pipe_drain(p);
     p->lat_ms.clear();
+    p->submit_ms.clear();
+    if (rc == XCORR_OK)
+        rc = set_anchor(p);   // the compute stream is idle after the drain
     return rc;
 }
 

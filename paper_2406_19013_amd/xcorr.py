@@ -63,6 +63,7 @@ class Stats(ctypes.Structure):
         ("seq_gaps_total", ctypes.c_uint64),
         ("tile", ctypes.c_int32),
         ("regions_per_chan", ctypes.c_int32),
+        ("tile_from_cache", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -78,6 +79,12 @@ class PipeStats(ctypes.Structure):
         ("p99_ms", ctypes.c_double),
         ("max_ms", ctypes.c_double),
         ("mean_ms", ctypes.c_double),
+        ("held", ctypes.c_int64),
+        ("submit_latencies", ctypes.c_int64),
+        ("submit_p50_ms", ctypes.c_double),
+        ("submit_p99_ms", ctypes.c_double),
+        ("submit_max_ms", ctypes.c_double),
+        ("clock_anchor_err_ms", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -140,6 +147,10 @@ def load(path: str | None = None):
             "xcorr_batch_destroy": [vp],
             "xcorr_autotune_query": [cfgp, ctypes.POINTER(sz)],
             "xcorr_autotune": [cfgp, vp, sz, vp, ctypes.POINTER(ctypes.c_int32)],
+            "xcorr_autotune_batch": [cfgp, vp, sz, vp, ctypes.POINTER(ctypes.c_int32)],
+            "xcorr_autotune_kernel": [cfgp, ctypes.c_int32, ctypes.c_char_p, sz],
+            "xcorr_plan_tile": [cfgp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                ctypes.POINTER(ctypes.c_int32)],
             "xcorr_pipe_query": [vp, ctypes.c_int, i64, ctypes.POINTER(sz)],
             "xcorr_pipe_init": [vp, ctypes.c_int, i64, i64, vp, sz, vp, vp, ctypes.POINTER(vp)],
             "xcorr_pipe_push": [vp, vp, ctypes.c_int, u64, vp, ctypes.POINTER(ctypes.c_int)],
@@ -312,13 +323,37 @@ def xcorr_autotune(cfg: Config, scratch, stream=None) -> int:
     return best.value
 
 
+def xcorr_autotune_batch(cfg: Config, scratch, stream=None) -> int:
+    best = ctypes.c_int32()
+    _check(load().xcorr_autotune_batch(ctypes.byref(cfg), ctypes.c_void_p(scratch.data_ptr()),
+                                       scratch.numel() * scratch.element_size(), _stream_handle(stream),
+                                       ctypes.byref(best)), "xcorr_autotune_batch")
+    return best.value
+
+
+def xcorr_autotune_kernel(cfg: Config, batch: bool = False) -> str:
+    """Name of the kernel the tuner times for this config (the one it runs)."""
+    buf = ctypes.create_string_buffer(96)
+    _check(load().xcorr_autotune_kernel(ctypes.byref(cfg), int(batch), buf, len(buf)), "xcorr_autotune_kernel")
+    return buf.value.decode()
+
+
+def xcorr_plan_tile(cfg: Config, batch: bool = False):
+    """(tile, from_cache) that xcorr_init (or xcorr_batch_init) would use."""
+    t, c = ctypes.c_int32(), ctypes.c_int32()
+    _check(load().xcorr_plan_tile(ctypes.byref(cfg), int(batch), ctypes.byref(t), ctypes.byref(c)),
+           "xcorr_plan_tile")
+    return t.value, bool(c.value)
+
+
 def autotune(n_inputs: int, n_chans: int, sample_bits: int = 4, path: int = PATH_I8_MFMA, device="cuda",
-             stream=None) -> int:
-    """Run the autotuner with a torch-allocated scratch; returns the best tile."""
+             stream=None, batch: bool = False) -> int:
+    """Run the autotuner (batch: on the batched kernel) with a torch-allocated
+    scratch; returns the best tile."""
     import torch
     cfg = make_config(n_inputs, n_chans, sample_bits, path)
     scratch = torch.empty(xcorr_autotune_query(cfg), dtype=torch.uint8, device=device)
-    return xcorr_autotune(cfg, scratch, stream)
+    return (xcorr_autotune_batch if batch else xcorr_autotune)(cfg, scratch, stream)
 
 
 def xcorr_pipe_query(ctx, n_slots: int, block_samples: int) -> int:
@@ -536,10 +571,19 @@ class Batch:
 class Pipe:
     """Streaming loop around one Correlator: a ring of device slots for host
     blocks, a copy stream and a compute stream (torch streams, default
-    priority), a dump every ``dump_every`` blocks, per-block latency."""
+    priority), a dump every ``dump_every`` blocks, per-block latency.
+
+    The pipe keeps a reference to every pushed block (and dump buffer) until
+    the compute stream has passed the launch that reads (writes) it, so a
+    caller may drop its own reference right after ``push``: a held device
+    block's ingest is enqueued only on a later call, and a pinned host block
+    is copied by the library outside torch's allocators, so neither torch's
+    stream recording nor its host cache would keep that memory alive."""
 
     def __init__(self, correlator, block_samples: int, dump_every: int, n_slots: int = 4,
                  host_blocks: bool = True, device="cuda"):
+        import collections
+
         import torch
         self.cor = correlator
         self.block_samples = block_samples
@@ -552,12 +596,29 @@ class Pipe:
         self.pipe = xcorr_pipe_init(correlator.ctx, n_slots, block_samples, dump_every, self.ring,
                                     self.copy_stream, self.compute_stream)
         self.seq = 0
+        self._unqueued = collections.deque()   # pushed tensors whose launch is not enqueued yet
+        self._inflight = collections.deque()   # (event after their launch, tensors)
+
+    def _settle(self):
+        """After a library call: the tensors of every push except the newest
+        `held` ones now have their launch on the compute stream; tag them with
+        an event there and let go of those whose event has passed."""
+        import torch
+        held = int(self.stats()["held"]) if self.pipe else 0
+        ready = []
+        while len(self._unqueued) > held:
+            ready.append(self._unqueued.popleft())
+        if ready:
+            ev = torch.cuda.Event()
+            ev.record(self.compute_stream)
+            self._inflight.append((ev, ready))
+        while self._inflight and self._inflight[0][0].query():
+            self._inflight.popleft()
 
     def push(self, block, out=None, seq: int | None = None) -> bool:
         """Submit one block (pinned host tensor or device tensor).  The pipe's
         streams are ordered after torch's current stream (where the block, the
-        output and the ring were produced), and the tensors are recorded on
-        them so that the caching allocator does not reuse them early."""
+        output and the ring were produced)."""
         import torch
         cur = torch.cuda.current_stream()
         self.copy_stream.wait_stream(cur)
@@ -569,10 +630,13 @@ class Pipe:
         s = self.seq if seq is None else seq
         dumped = xcorr_pipe_push(self.pipe, block, not block.is_cuda, s, out)
         self.seq = s + 1
+        self._unqueued.append((block, out))
+        self._settle()
         return dumped
 
     def set_fuse(self, fuse: int):
         xcorr_pipe_set_fuse(self.pipe, fuse)
+        self._settle()
 
     def dump(self, out):
         """End the integration now (dump_every = 0 pipes dump only here):
@@ -580,21 +644,34 @@ class Pipe:
         import torch
         self.compute_stream.wait_stream(torch.cuda.current_stream())
         out.record_stream(self.compute_stream)
-        return xcorr_pipe_dump(self.pipe, out)
+        r = xcorr_pipe_dump(self.pipe, out)
+        self._unqueued.append((out,))
+        self._settle()
+        return r
 
     def drain(self):
         xcorr_pipe_drain(self.pipe)
+        self._settle()
+        self._inflight.clear()   # the drain waited for every launch
 
     def stats(self) -> dict:
         return xcorr_pipe_stats(self.pipe)
 
     def reset_latency(self):
         xcorr_pipe_reset_latency(self.pipe)
+        self._settle()
+        self._inflight.clear()
 
     def close(self):
+        """Ingest what is held, wait for the streams, destroy the pipe."""
         if self.pipe:
-            xcorr_pipe_destroy(self.pipe)
-            self.pipe = None
+            try:
+                xcorr_pipe_drain(self.pipe)
+            finally:
+                xcorr_pipe_destroy(self.pipe)
+                self.pipe = None
+                self._unqueued.clear()
+                self._inflight.clear()
 
     def __del__(self):
         try:

@@ -104,10 +104,11 @@ def test_batch_calls_reject_bad_arguments_on_the_host(lib):
 def test_autotune_query_sizes_and_rejections():
     cfg = X.make_config(192, 1024, 4, X.PATH_I8_MFMA)
     ws, _, _ = X.xcorr_query(cfg)
-    assert X.xcorr_autotune_query(cfg) == ws + 2048 * 1024 * 192
+    # accumulators + input block + the batched kernel's queue counters
+    assert X.xcorr_autotune_query(cfg) == ws + 2048 * 1024 * 192 + 256
     cfg8 = X.make_config(96, 16, 8, X.PATH_F16_MFMA)
     ws8, _, _ = X.xcorr_query(cfg8)
-    assert X.xcorr_autotune_query(cfg8) == ws8 + 2048 * 16 * 96 * 2
+    assert X.xcorr_autotune_query(cfg8) == ws8 + 2048 * 16 * 96 * 2 + 256
     with pytest.raises(X.XcorrError) as ei:
         X.xcorr_autotune_query(X.make_config(16, 8, 4, X.PATH_PLAIN))
     assert ei.value.code == X.XCORR_E_INVAL
@@ -160,3 +161,48 @@ def test_pipe_calls_reject_bad_arguments_on_the_host(lib):
     assert lib.xcorr_pipe_stats(None, None) == X.XCORR_E_INVAL
     assert lib.xcorr_pipe_destroy(None) == X.XCORR_E_INVAL
     assert not p.value
+
+
+def test_tuner_times_the_kernel_the_context_runs(monkeypatch):
+    """The tuner labels its cache line with the kernel it timed, which is the
+    kernel an ingest of the same config launches."""
+    monkeypatch.delenv("XCORR_MFMA4_VARIANT", raising=False)
+    c4 = X.make_config(192, 1024, 4, X.PATH_I8_MFMA)
+    assert X.xcorr_autotune_kernel(c4) == "xc_mfma4f_kernel"
+    assert X.xcorr_autotune_kernel(c4, batch=True) == "xc_batch4_kernel"
+    assert X.xcorr_autotune_kernel(X.make_config(192, 512, 8, X.PATH_I8_MFMA)) == "xc_mfma8_kernel_i8"
+    assert X.xcorr_autotune_kernel(X.make_config(192, 512, 8, X.PATH_F16_MFMA)) == "xc_mfma8_kernel_f16"
+    monkeypatch.setenv("XCORR_MFMA4_VARIANT", "roles")
+    assert X.xcorr_autotune_kernel(c4) == "xc_mfma4_kernel"
+    with pytest.raises(X.XcorrError):
+        X.xcorr_autotune_kernel(X.make_config(192, 512, 8, X.PATH_I8_MFMA), batch=True)
+
+
+def test_tune_cache_lines_are_used_only_for_their_kernel(tmp_path, monkeypatch):
+    """xcorr_init and xcorr_batch_init take the last cache line of their config
+    that names the kernel they will run; lines of other kernels, other configs
+    and the old five-field format are ignored."""
+    monkeypatch.delenv("XCORR_MFMA4_VARIANT", raising=False)
+    cache = tmp_path / "tune.txt"
+    cache.write_text("4 192 1024 1 3\n"                          # old format: ignored
+                     "4 192 1024 1 2 xc_mfma4_kernel\n"           # per-role kernel: not run
+                     "4 192 1024 1 4 xc_mfma4f_kernel\n"
+                     "4 192 512 1 3 xc_mfma4f_kernel\n"           # another config
+                     "4 192 1024 1 3 xc_batch4_kernel\n"
+                     "4 192 1024 1 5 xc_batch4_kernel\n")          # 5 is not a batch tile: ignored
+    monkeypatch.setenv("XCORR_TUNE_CACHE", str(cache))
+    cfg = X.make_config(192, 1024, 4, X.PATH_I8_MFMA)
+    assert X.xcorr_plan_tile(cfg) == (4, True)
+    assert X.xcorr_plan_tile(cfg, batch=True) == (3, True)
+    monkeypatch.setenv("XCORR_MFMA4_VARIANT", "roles")
+    assert X.xcorr_plan_tile(cfg) == (2, True)
+    monkeypatch.delenv("XCORR_MFMA4_VARIANT")
+    # an explicit tile wins over the cache; no line: the built-in choice
+    assert X.xcorr_plan_tile(X.make_config(192, 1024, 4, X.PATH_I8_MFMA, tile=3)) == (3, False)
+    assert X.xcorr_plan_tile(X.make_config(256, 64, 4, X.PATH_I8_MFMA)) == (4, False)
+    # a batch member without a batch line keeps its own tile if the batched
+    # kernel carries it, else the 2..4 tile that pads least
+    assert X.xcorr_plan_tile(X.make_config(192, 512, 4, X.PATH_I8_MFMA), batch=True) == (3, False)
+    assert X.xcorr_plan_tile(X.make_config(160, 8, 4, X.PATH_I8_MFMA, tile=5), batch=True)[0] in (2, 3, 4)
+    monkeypatch.delenv("XCORR_TUNE_CACHE")
+    assert X.xcorr_plan_tile(cfg) == (6, False)

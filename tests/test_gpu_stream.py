@@ -73,15 +73,18 @@ def test_pipe_refuses_integration_past_the_int32_bound():
     c.close()
 
 
-def test_streaming_workload_first_dump_sampled():
+@pytest.mark.parametrize("fuse", [1, 8])
+def test_streaming_workload_first_dump_sampled(fuse):
     """192 inputs x 4096 channels, 1024-sample blocks from a pool of 4
     device-resident blocks in rotation, one dump per 128 blocks (131,072
-    samples): the dump equals the oracle on 8 sampled channels."""
+    samples), one launch per block or 8 blocks per launch (as the benchmark
+    runs them): the dump equals the oracle on 8 sampled channels."""
     N, F, B, every, pool_n = 192, 4096, 1024, 128, 4
-    _say("streaming workload: generating the block pool")
+    _say(f"streaming workload fuse={fuse}: generating the block pool")
     pool = [synth.stream_block(N, F, k, array_id=1, device="cuda") for k in range(pool_n)]
     c = X.Correlator(N, F, 4, X.PATH_I8_MFMA)
     p = X.Pipe(c, B, every, host_blocks=False)
+    p.set_fuse(fuse)
     out = torch.empty((F, N * (N + 1) // 2, 2), dtype=torch.int32, device="cuda")
     for k in range(every):
         p.push(pool[k % pool_n], out=out)
@@ -104,6 +107,8 @@ def test_streaming_workload_first_dump_sampled():
         assert np.array_equal(got[ci], oracle.to_int32(want[ci])), chans[ci]
     st = p.stats()
     assert st["dumps"] == 1 and st["blocks"] == every
+    assert st["latencies"] == every // fuse and st["submit_latencies"] == every
+    assert st["submit_p50_ms"] > 0 and st["submit_p99_ms"] <= st["submit_max_ms"]
     p.close()
     c.close()
 
@@ -155,5 +160,37 @@ def test_pipe_fuses_device_blocks():
     assert st["blocks"] == 10 and st["dumps"] == 1 and st["latencies"] == 4
     # 4 fused launches (3, 3, 1, 3 blocks) and one dump inside the pipe, one dump above
     assert c.stats()["kernel_launches"] == 4 + 2
+    p.close()
+    c.close()
+
+
+@pytest.mark.parametrize("host", [False, True], ids=["device_blocks", "host_blocks"])
+def test_pipe_keeps_dropped_blocks_alive(host):
+    """The caller drops each block right after pushing it and allocates a
+    block-sized tensor of junk: with 8 device blocks held per launch (or a
+    pinned host block copied by the library) the pipe must keep the block's
+    memory until its launch has read it, or the junk would be correlated."""
+    N, F, B, nb = 64, 8, 256, 16
+    src = [synth.uniform_volts4(N, F, B, seed=(4020, k)) for k in range(nb)]
+    c = X.Correlator(N, F, 4, X.PATH_I8_MFMA)
+    p = X.Pipe(c, B, 0, n_slots=2, host_blocks=host)
+    if not host:
+        p.set_fuse(8)
+    junk = []
+    for k in range(nb):
+        blk = src[k].pin_memory() if host else src[k].cuda()
+        p.push(blk)
+        del blk
+        j = torch.empty((B, F, N), dtype=torch.uint8).pin_memory() if host else \
+            torch.empty((B, F, N), dtype=torch.uint8, device="cuda")
+        j.fill_(0x77)
+        junk.append(j)
+    out = torch.empty((F, N * (N + 1) // 2, 2), dtype=torch.int32, device="cuda")
+    n, _ = p.dump(out)
+    p.drain()
+    torch.cuda.synchronize()
+    assert n == nb * B and p.stats()["held"] == 0
+    v = torch.cat(src)
+    assert np.array_equal(out.cpu().numpy(), oracle.to_int32(oracle.xcorr(v.numpy(), 4, nb * B, F, N)))
     p.close()
     c.close()
