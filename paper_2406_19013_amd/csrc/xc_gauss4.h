@@ -1,0 +1,598 @@
+// Device code of the three-product 4+4-bit int8-MFMA path.
+//
+// Per channel the packed voltages form a matrix X[i][t], one byte per sample
+// (high nibble re, low nibble im, two's complement).  Three int8 forms of a
+// byte x are exact and cost one bit operation each:
+//     A = x ^ 0x08 = 16 re + im + 8,   B = x ^ 0x07 = 16 re - im + 7,
+//     R = x & 0xF0 = 16 re                               (all in [-128, 127]).
+// Over a set of samples (padding samples are zero bytes and count as zero
+// voltages) the three real products
+//     P_ab = A_i B_j^T,  P_ba = B_i A_j^T,  P_rr = R_i R_j^T
+// give the visibility exactly (with SR_k = sum R_k, SA_k = sum A_k,
+// g_k = 16 SR_k - 15 SA_k, h_k = 16 SR_k - SA_k, and Tp the padded count):
+//     32 Im V_ij = P_ab - P_ba + g_i - g_j
+//      2 Sum im_i im_j = 2 P_rr - P_ab - P_ba + h_i + h_j + 128 Tp
+//     Re V_ij = P_rr / 256 + Sum im_i im_j
+// so a tile costs three MFMAs per K step instead of the four real products of
+// the direct form, and on a diagonal tile P_ba is the transpose of P_ab: two.
+// Every product is an exact integer; |A B| and |R R| are at most 2^14 per
+// sample, so each accumulator stays below 2^31 for up to 131,071 samples, and
+// the combinations are evaluated in wrapping 32-bit arithmetic, whose result
+// is exact because the true values (32 Im, 2 II) fit in int32.
+//
+// Work split.  One work-group per channel region (here: the whole triangle of
+// D 32-input blocks, D <= 6), persistent: each work-group walks its channels
+// as one continuous stream of 64-sample chunks through an LDS ring, so the
+// next channel's first chunks are in flight while the current channel's
+// results are stored.  The triangle's tiles, in row-major order, are cut into
+// 8 contiguous segments of near-equal MFMA count, one per wave, and the
+// segments are placed so that the two waves sharing a SIMD carry
+// complementary loads.  A wave owns every product of its tiles, combines them
+// in registers and stores the visibilities directly (no staging), except the
+// transposed P_ab of a diagonal tile, which goes through a small LDS tile.
+#pragma once
+#include "xc_mfma4.h"
+
+namespace xc {
+namespace {
+
+// ---- compile-time work split of a triangle of D blocks over 8 waves --------
+
+constexpr int g3_ntiles(int D) { return D * (D + 1) / 2; }
+constexpr bool g3_diag(int t) { return tri_I(t) == tri_J(t); }
+constexpr int g3_abs(int x) { return x < 0 ? -x : x; }
+
+// Waves per work-group.  Four (one per SIMD, 512 registers each) keep the
+// accumulators in AGPRs and give every wave a long run of independent MFMAs
+// under which it unpacks the next step's operands.
+#ifndef XC_G3_WAVES
+#define XC_G3_WAVES 8
+#endif
+constexpr int kG3Waves = XC_G3_WAVES;
+constexpr int kG3Threads = 64 * kG3Waves;
+
+// The split, evaluated once per D: wave slot s takes tiles [t0[s], t1[s]).
+// Tiles in row-major order are cut into W contiguous segments at the
+// boundaries whose cumulative MFMA count (3 per off-diagonal tile, 2 per
+// diagonal tile) is closest to k/W of the total.  With 8 waves (two per
+// SIMD) the four largest segments take slots 0..3 and the others slots
+// 7..4, so that slot s and slot s + 4 pair the r-th largest segment with the
+// r-th smallest; with 4 waves slot s takes segment s.
+struct G3Split {
+    int t0[8], t1[8];
+    int units[8];
+    int sum_owner[6];   // wave slot that sums the forms of block b
+};
+constexpr G3Split g3_make_split(int D, int W)
+{
+    G3Split sp{};
+    const int NT = g3_ntiles(D);
+    int cum[6 * 7 / 2 + 1] = {};
+    int row = 0, col = 0;
+    for (int t = 0; t < NT; ++t) {
+        cum[t + 1] = cum[t] + (row == col ? 2 : 3);
+        if (col == row) {
+            ++row;
+            col = 0;
+        } else {
+            ++col;
+        }
+    }
+    const int U = cum[NT];
+    int bound[9] = {};
+    for (int k = 1; k < W; ++k) {
+        int best = 0;
+        for (int b = 0; b <= NT; ++b)
+            if (g3_abs(W * cum[b] - k * U) < g3_abs(W * cum[best] - k * U))
+                best = b;
+        bound[k] = best;
+    }
+    bound[W] = NT;
+    int su[8] = {};
+    for (int k = 0; k < W; ++k)
+        su[k] = cum[bound[k + 1]] - cum[bound[k]];
+    for (int k = 0; k < W; ++k) {
+        int slot = k;
+        if (W == 8) {
+            int r = 0;
+            for (int m = 0; m < 8; ++m)
+                if (su[m] > su[k] || (su[m] == su[k] && m < k))
+                    ++r;
+            slot = r < 4 ? r : 4 + (7 - r);
+        }
+        sp.t0[slot] = bound[k];
+        sp.t1[slot] = bound[k + 1];
+        sp.units[slot] = su[k];
+    }
+    // the per-block sums go to the wave, among those that read the block,
+    // with the least work so far (MFMA units plus 3 per block already summed)
+    int load[8] = {};
+    for (int s = 0; s < W; ++s)
+        load[s] = sp.units[s];
+    for (int b = 0; b < D; ++b) {
+        int best = -1;
+        for (int s = 0; s < W; ++s) {
+            bool uses = false;
+            int r = 0, c = 0;
+            for (int t = 0; t < NT; ++t) {
+                if (t >= sp.t0[s] && t < sp.t1[s] && (r == b || c == b))
+                    uses = true;
+                if (c == r) {
+                    ++r;
+                    c = 0;
+                } else {
+                    ++c;
+                }
+            }
+            if (uses && (best < 0 || load[s] < load[best]))
+                best = s;
+        }
+        sp.sum_owner[b] = best;
+        if (best >= 0)
+            load[best] += 3;
+    }
+    return sp;
+}
+template <int D>
+constexpr G3Split kG3Split = g3_make_split(D, kG3Waves);
+
+template <int D>
+constexpr int g3_t0(int s) { return kG3Split<D>.t0[s]; }
+template <int D>
+constexpr int g3_t1(int s) { return kG3Split<D>.t1[s]; }
+template <int D>
+constexpr bool g3_uses_block(int s, int b)
+{
+    for (int t = g3_t0<D>(s); t < g3_t1<D>(s); ++t)
+        if (tri_I(t) == b || tri_J(t) == b)
+            return true;
+    return false;
+}
+template <int D>
+constexpr bool g3_owns_sums(int s, int b)
+{
+    return kG3Split<D>.sum_owner[b] == s;
+}
+// Order in which a wave unpacks its blocks within a K step: the row block of
+// its first tile first (shared by most of its tiles), then the others in
+// increasing order.  pos < 0 for a block the wave does not read.
+template <int D>
+constexpr int g3_block_pos(int s, int b)
+{
+    if (!g3_uses_block<D>(s, b))
+        return -1;
+    const int first = g3_t0<D>(s) < g3_t1<D>(s) ? tri_I(g3_t0<D>(s)) : 0;
+    if (b == first)
+        return 0;
+    int p = 1;
+    for (int c = 0; c < b; ++c)
+        if (c != first && g3_uses_block<D>(s, c))
+            ++p;
+    return p;
+}
+// a tile's MFMAs go right after the later of its two blocks is unpacked
+template <int D>
+constexpr int g3_tile_pos(int s, int t)
+{
+    const int a = g3_block_pos<D>(s, tri_I(t)), b = g3_block_pos<D>(s, tri_J(t));
+    return a > b ? a : b;
+}
+template <int D>
+constexpr int g3_mfmas_of(int s)
+{
+    int n = 0;
+    for (int t = g3_t0<D>(s); t < g3_t1<D>(s); ++t)
+        n += g3_diag(t) ? 2 : 3;
+    return n;
+}
+
+// LDS transpose slot of a diagonal tile: its block
+constexpr int g3_diag_slot(int t) { return tri_I(t); }
+
+// ---- resources ---------------------------------------------------------------
+
+constexpr int g3_wgs_per_cu(int D) { return D <= 3 ? 2 : 1; }
+// waves of this kernel per SIMD
+constexpr int g3_waves_per_eu(int D) { return g3_wgs_per_cu(D) * kG3Waves / 4; }
+constexpr int g3_nbuf(int D) { return D <= 3 ? 4 : 8; }
+constexpr int kG3Chunk = 64;                             // time rows per ring slot
+#ifndef XC_G3_CPB
+#define XC_G3_CPB 2
+#endif
+constexpr int kG3ChunksPerBarrier = XC_G3_CPB;             // chunks per work-group barrier
+constexpr int kG3TileStride = 33;                        // ints per row of a transpose tile
+constexpr int g3_ring_bytes(int D) { return g3_nbuf(D) * kG3Chunk * kRowBytes; }
+constexpr int g3_tr_bytes(int D) { return D * 32 * kG3TileStride * 4; }
+constexpr int g3_gh_bytes(int D) { return D * 32 * 8; }
+constexpr int g3_smem_bytes(int D) { return g3_ring_bytes(D) + g3_tr_bytes(D) + g3_gh_bytes(D); }
+
+// LDS-only wait: outstanding LDS operations of this wave done, memory
+// operations in flight left alone (vmcnt and expcnt at their maxima).
+__device__ __forceinline__ void wait_lgkm0() { __builtin_amdgcn_s_waitcnt(0xF | (3 << 14) | (7 << 4)); }
+
+// Source of a launch: one contiguous input, or a table of caller blocks that
+// hold whole 64-sample chunks (chunk c of an item is chunk c % cpb of block
+// c / cpb; every channel item walks the same table).
+struct G3Src {
+    const uint8_t *volts;
+    const BlockTable *bt;
+};
+
+struct G3Args {
+    const uint8_t *volts;   // [T][F][N] packed (MB = 0)
+    int64_t T;              // samples (MB = 1: n_blocks * cpb * 64)
+    int F, N;
+    int per;                // channels per XCD range
+    int2 *out;              // [F][P] results
+    const int2 *in;         // [F][P] running sums (ACC = 1)
+};
+
+// One wave's share of a launch: its tiles of every channel item of its
+// work-group, K loop over the continuous chunk stream, and the epilogue of
+// each item.
+template <int D, int SLOT, int ACC, int MB>
+__device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const BlockTable *bt,
+                                        const uint8_t *__restrict__ volts)
+{
+    constexpr int NBUF = g3_nbuf(D);
+    constexpr int KC = kG3Chunk;
+    constexpr int BUF = KC * kRowBytes;
+    constexpr int LOADS = KC * 16 / kG3Threads;         // 16-byte DMA units per lane per chunk
+    constexpr int T0 = g3_t0<D>(SLOT), T1 = g3_t1<D>(SLOT);
+    constexpr int NT = T1 > T0 ? T1 - T0 : 1;
+
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    if constexpr (g3_waves_per_eu(D) == 1) {
+        // an AGPR operand in the function makes the compiler take the MFMA
+        // forms that accumulate in AGPRs (with one wave per SIMD it then
+        // has 256 of each)
+        int hint = 0;
+        asm volatile("" : "+a"(hint));
+    }
+    const int lane = tid & 63;
+    const int g = lane >> 4, q = lane & 15;
+    lds_u8 *const ring = (lds_u8 *)smem;
+    int *const trs = (int *)(smem + g3_ring_bytes(D));                        // transpose tiles
+    int *const gh = (int *)(smem + g3_ring_bytes(D) + g3_tr_bytes(D));       // g, h per input
+
+    // this work-group's channels: the local items m, m + M, ... of its XCD's range
+    const int xcd = blockIdx.x & 7, m = blockIdx.x >> 3, M = gridDim.x >> 3;
+    const int r0 = xcd * a.per;
+    const int rlen = min(a.per, a.F - r0);
+    const int n_my = rlen > m ? (rlen - m + M - 1) / M : 0;
+    const int nch = (int)((a.T + KC - 1) / KC);
+    const int total = n_my * nch;
+    if (total == 0)
+        return;
+    const int64_t row_bytes = (int64_t)a.F * a.N;
+    const int64_t chunk_bytes = KC * row_bytes;
+    const int Tp = nch * KC;
+
+    // DMA share of this wave: unit U = (SLOT * LOADS + k) * 64 + lane of a
+    // chunk -> time row U / 16, position U % 16 (swizzled unit p); the lane
+    // offsets of channel f (recomputed when the issue pointer reaches the
+    // next channel, so nothing is held across the K loop for it)
+    auto dma_offset = [&](int k, int f) {
+        const int U = (SLOT * LOADS + k) * 64 + lane;
+        const int r = U >> 4;
+        const int p = (U & 15) ^ ((r & 7) << 1);
+        return p < 2 * D && 16 * p < a.N ? (int)(r * row_bytes) + f * a.N + 16 * p : kBufferOutOfRange;
+    };
+    // operand read offsets (see frag_tr8): row (g >> 1) * 16 + (q >> 1) of the
+    // K step, unit 2b + (g & 1) swizzled
+    const int row_off = ((g >> 1) * 16 + (q >> 1)) * kRowBytes + (q & 1) * 8;
+    int colo[D];
+#pragma unroll
+    for (int b = 0; b < D; ++b)
+        colo[b] = ((2 * b + (g & 1)) ^ (q & 14)) << 4;
+
+    // issue state (wave-uniform): item and chunk of the next chunk to issue
+    int is_k = 0, is_c = 0;
+    int voff[LOADS];
+    auto set_issue_item = [&](int k) {
+        const int f = r0 + m + k * M;
+#pragma unroll
+        for (int u = 0; u < LOADS; ++u)
+            voff[u] = dma_offset(u, f);
+    };
+    set_issue_item(0);
+    auto issue_next = [&](int bufi) {
+        const uint8_t *src;
+        int records;
+        if constexpr (MB) {
+            // addressed from the first block (the restrict-qualified base)
+            src = volts + (bt->p[is_c / bt->chunks_per_block] - bt->p[0]) +
+                  (int64_t)(is_c % bt->chunks_per_block) * chunk_bytes;
+            records = (int)chunk_bytes;
+        } else {
+            src = volts + (int64_t)is_c * chunk_bytes;
+            const int64_t rows = min((int64_t)KC, a.T - (int64_t)is_c * KC);
+            records = (int)(rows * row_bytes);
+        }
+        __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc((void *)src, (short)0, records, 0x00020000);
+        lds_u8 *dst = ring + bufi * BUF + SLOT * LOADS * 1024;
+#pragma unroll
+        for (int k = 0; k < LOADS; ++k)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (__attribute__((address_space(3))) void *)(dst + k * 1024),
+                                                     16, voff[k], 0, 0, kStreamLoadPolicy);
+        if (++is_c == nch) {
+            is_c = 0;
+            if (++is_k < n_my)
+                set_issue_item(is_k);
+        }
+    };
+
+    v16i acc_ab[NT], acc_ba[NT], acc_rr[NT];
+    int sr[D], sa[D], sr2[D], sa2[D];
+    auto clear = [&]() {
+        static_for<0, NT>([&](auto tc) {
+            acc_ab[tc] = v16i{};
+            acc_ba[tc] = v16i{};
+            acc_rr[tc] = v16i{};
+        });
+        static_for<0, D>([&](auto bc) {
+            sr[bc] = 0;
+            sa[bc] = 0;
+            sr2[bc] = 0;
+            sa2[bc] = 0;
+        });
+    };
+    clear();
+
+    // The K loop is a two-stage pipeline over 32-sample K steps: while the
+    // MFMAs of one step run, the next step's operands are read from LDS and
+    // unpacked into the other register set.  raw: the packed bytes of a step;
+    // A, B, R: its three forms; the owner of a block also sums its forms.
+    auto read_step = [&](lds_u8 *cb, int koff, v4i *X) {
+        static_for<0, D>([&](auto bc) {
+            constexpr int b = bc;
+            if constexpr (g3_uses_block<D>(SLOT, b))
+                X[b] = frag_tr8<8 * kRowBytes>(cb + colo[b] + koff);
+        });
+    };
+    auto unpack = [&](const v4i *X, v4i *A, v4i *B, v4i *R) {
+        static_for<0, D>([&](auto bc) {
+            constexpr int b = bc;
+            if constexpr (g3_uses_block<D>(SLOT, b)) {
+                A[b] = X[b] ^ 0x08080808;
+                B[b] = X[b] ^ 0x07070707;
+                R[b] = X[b] & (int)0xF0F0F0F0;
+                if constexpr (g3_owns_sums<D>(SLOT, b)) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        sr[b] = __builtin_amdgcn_sdot4(R[b][k], 0x01010101, sr[b], false);
+                        sa[b] = __builtin_amdgcn_sdot4(A[b][k], 0x01010101, sa[b], false);
+                    }
+                }
+            }
+        });
+    };
+    // the step's MFMAs, independent accumulators back to back
+    auto mfmas = [&](const v4i *A, const v4i *B, const v4i *R) {
+        static_for<T0, T1>([&](auto tc) {
+            constexpr int t = tc;
+            acc_ab[t - T0] = mfma_i8(A[tri_I(t)], B[tri_J(t)], acc_ab[t - T0]);
+        });
+        static_for<T0, T1>([&](auto tc) {
+            constexpr int t = tc;
+            if constexpr (!g3_diag(t))
+                acc_ba[t - T0] = mfma_i8(B[tri_I(t)], A[tri_J(t)], acc_ba[t - T0]);
+        });
+        static_for<T0, T1>([&](auto tc) {
+            constexpr int t = tc;
+            acc_rr[t - T0] = mfma_i8(R[tri_I(t)], R[tri_J(t)], acc_rr[t - T0]);
+        });
+    };
+
+    // epilogue of one channel: combine, descale and store this wave's tiles
+    auto epilogue = [&](int f) {
+        // per-input sums: lanes l and l + 32 hold the two K halves of input l % 32
+        static_for<0, D>([&](auto bc) {
+            constexpr int b = bc;
+            if constexpr (g3_owns_sums<D>(SLOT, b)) {
+                const int srl = sr[b] + sr2[b], sal = sa[b] + sa2[b];
+                const int srt = srl + __shfl_xor(srl, 32);
+                const int sat = sal + __shfl_xor(sal, 32);
+                if (lane < 32)
+                    *(int2 *)&gh[(b * 32 + lane) * 2] = make_int2(16 * srt - 15 * sat, 16 * srt - sat);
+            }
+        });
+        wait_lgkm0();
+        barrier_no_fence();
+        const int64_t P = (int64_t)a.N * (a.N + 1) / 2;
+        int2 *const out_f = a.out + (int64_t)f * P;
+        const int2 *const in_f = a.in + (int64_t)f * P;
+        const int jl = lane & 31;
+        const int il0 = 4 * (lane >> 5);
+        static_for<T0, T1>([&](auto tc) {
+            constexpr int t = tc;
+            constexpr int I = tri_I(t), J = tri_J(t);
+            constexpr bool diag = g3_diag(t);
+            const int j = J * 32 + jl;
+            const int2 ghj = *(const int2 *)&gh[j * 2];
+            v16i ba;
+            if constexpr (diag) {
+                // P_ba of a diagonal tile is the transpose of its P_ab
+                int *const tr = trs + g3_diag_slot(t) * 32 * kG3TileStride;
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    tr[(8 * (r >> 2) + il0 + (r & 3)) * kG3TileStride + jl] = acc_ab[t - T0][r];
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    ba[r] = tr[jl * kG3TileStride + 8 * (r >> 2) + il0 + (r & 3)];
+            } else {
+                ba = acc_ba[t - T0];
+            }
+#pragma unroll
+            for (int r4 = 0; r4 < 4; ++r4) {
+                const int ib = I * 32 + 8 * r4 + il0;     // rows ib .. ib + 3
+                // running sums of these rows (ACC = 1), from a valid address
+                // where the pair does not exist
+                int2 old[4];
+                if constexpr (ACC) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int i = ib + u;
+                        const bool ok = i < a.N && (!diag || j <= i);
+                        old[u] = in_f[ok ? (int64_t)i * (i + 1) / 2 + j : 0];
+                    }
+                }
+                const int4 ghi01 = *(const int4 *)&gh[ib * 2];
+                const int4 ghi23 = *(const int4 *)&gh[ib * 2 + 4];
+                const int gi[4] = {ghi01.x, ghi01.z, ghi23.x, ghi23.z};
+                const int hi[4] = {ghi01.y, ghi01.w, ghi23.y, ghi23.w};
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int r = 4 * r4 + u;
+                    const int i = ib + u;
+                    const uint32_t ab = (uint32_t)acc_ab[t - T0][r], bav = (uint32_t)ba[r];
+                    const uint32_t rr = (uint32_t)acc_rr[t - T0][r];
+                    const int im = (int)(ab - bav + (uint32_t)gi[u] - (uint32_t)ghj.x) >> 5;
+                    const int ii = (int)(2u * rr - ab - bav + (uint32_t)hi[u] + (uint32_t)ghj.y + 128u * (uint32_t)Tp) >> 1;
+                    int re = (acc_rr[t - T0][r] >> 8) + ii;
+                    int imv = im;
+                    if constexpr (ACC) {
+                        re += old[u].x;
+                        imv += old[u].y;
+                    }
+                    if (i < a.N && (!diag || j <= i))
+                        out_f[(int64_t)i * (i + 1) / 2 + j] = make_int2(re, imv);
+                }
+            }
+        });
+    };
+
+    // Chunks are waited for and their slots recycled in groups of CPB: one
+    // work-group barrier per group.  The prologue fills every slot, waits for
+    // the first group and reads the packed operands of its first K step.
+    constexpr int CPB = kG3ChunksPerBarrier;
+    static_assert(CPB >= 1 && CPB < NBUF, "groups must leave chunks in flight");
+    int n_issued = 0;
+#pragma unroll
+    for (int c = 0; c < NBUF; ++c)
+        if (c < total) {
+            issue_next(c);
+            ++n_issued;
+        }
+    wait_vmcnt_chunks<LOADS, NBUF - 1>(n_issued - 1 - min(CPB - 1, total - 1));
+    barrier_no_fence();
+    v4i X0[D], X1[D];      // packed operands of the current and the next K step
+    read_step(ring + row_off, 0, X0);
+
+    // one K step: unpack its operands and issue its MFMAs
+    // Dataflow order: unpack one block, then issue the MFMAs of the tiles
+    // that block completes, then the next block, whose unpack runs under
+    // those MFMAs; the scheduling groups at the end keep MFMAs and VALU work
+    // interleaved (one MFMA, then up to 6 VALU instructions).
+    auto step = [&](const v4i *X) {
+        v4i A[D], B[D], R[D];
+        static_for<0, D>([&](auto kc) {
+            constexpr int k = kc;
+            static_for<0, D>([&](auto bc) {
+                constexpr int b = bc;
+                if constexpr (g3_block_pos<D>(SLOT, b) == k) {
+                    A[b] = X[b] ^ 0x08080808;
+                    B[b] = X[b] ^ 0x07070707;
+                    R[b] = X[b] & (int)0xF0F0F0F0;
+                    if constexpr (g3_owns_sums<D>(SLOT, b)) {
+                        // four short chains instead of two long ones
+                        sr[b] = __builtin_amdgcn_sdot4(R[b][0], 0x01010101, sr[b], false);
+                        sa[b] = __builtin_amdgcn_sdot4(A[b][0], 0x01010101, sa[b], false);
+                        sr2[b] = __builtin_amdgcn_sdot4(R[b][1], 0x01010101, sr2[b], false);
+                        sa2[b] = __builtin_amdgcn_sdot4(A[b][1], 0x01010101, sa2[b], false);
+                        sr[b] = __builtin_amdgcn_sdot4(R[b][2], 0x01010101, sr[b], false);
+                        sa[b] = __builtin_amdgcn_sdot4(A[b][2], 0x01010101, sa[b], false);
+                        sr2[b] = __builtin_amdgcn_sdot4(R[b][3], 0x01010101, sr2[b], false);
+                        sa2[b] = __builtin_amdgcn_sdot4(A[b][3], 0x01010101, sa2[b], false);
+                    }
+                }
+            });
+            static_for<T0, T1>([&](auto tc) {
+                constexpr int t = tc;
+                if constexpr (g3_tile_pos<D>(SLOT, t) == k) {
+                    acc_ab[t - T0] = mfma_i8(A[tri_I(t)], B[tri_J(t)], acc_ab[t - T0]);
+                    if constexpr (!g3_diag(t))
+                        acc_ba[t - T0] = mfma_i8(B[tri_I(t)], A[tri_J(t)], acc_ba[t - T0]);
+                    acc_rr[t - T0] = mfma_i8(R[tri_I(t)], R[tri_J(t)], acc_rr[t - T0]);
+                }
+            });
+        });
+        static_for<0, g3_mfmas_of<D>(SLOT)>([&](auto) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
+            __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);   // up to six VALU
+        });
+    };
+
+    int bufc = 0;          // ring slot of chunk gi
+    int ck = 0, cc = 0;    // item, and chunk within the item, being computed
+    for (int gi = 0; gi < total; ++gi) {
+        lds_u8 *const cb = ring + bufc * BUF + row_off;
+        const int nbufc = bufc + 1 == NBUF ? 0 : bufc + 1;
+        // first K step of chunk gi; the second step's operands are read
+        // meanwhile
+        read_step(cb, 32 * kRowBytes, X1);
+        step(X0);
+        const bool more = gi + 1 < total;
+        const bool item_end = cc + 1 == nch;
+        if (more && (gi + 1) % CPB == 0) {
+            // Next group gi + 1 .. gi + CPB: complete when this wave has at
+            // most the chunks issued after it outstanding (loads complete in
+            // order; the stores of an earlier epilogue only make the wait
+            // longer).  After the barrier every wave has read both steps of
+            // this group's chunks (each waits for its LDS reads first), so
+            // their slots take the next chunks of the stream.
+            const int last = min(gi + CPB, total - 1);
+            wait_vmcnt_chunks<LOADS, NBUF - 1>(n_issued - 1 - last);
+            wait_lgkm0();
+            barrier_no_fence();
+            int slot = bufc - (CPB - 1);
+            slot = slot < 0 ? slot + NBUF : slot;
+#pragma unroll
+            for (int k = 0; k < CPB; ++k) {
+                if (n_issued < total) {
+                    issue_next(slot);
+                    ++n_issued;
+                }
+                slot = slot + 1 == NBUF ? 0 : slot + 1;
+            }
+        }
+        // second K step of chunk gi, with the next chunk's first step read
+        // meanwhile unless an item ends here
+        lds_u8 *const nb = ring + nbufc * BUF + row_off;
+        if (more && !item_end)
+            read_step(nb, 0, X0);
+        step(X1);
+        if (item_end) {
+            epilogue(r0 + m + ck * M);
+            clear();
+            if (more)
+                read_step(nb, 0, X0);
+        }
+        bufc = nbufc;
+        if (item_end) {
+            cc = 0;
+            ++ck;
+        } else {
+            ++cc;
+        }
+    }
+}
+
+template <int D, int ACC, int MB>
+__device__ __forceinline__ void g3_dispatch(uint8_t *smem, const G3Args &a, const BlockTable *bt)
+{
+    switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {
+#define XC_CASE(W)                                        \
+    case W:                                               \
+        if constexpr (W < kG3Waves)                       \
+            g3_wave<D, W, ACC, MB>(smem, a, bt, a.volts); \
+        break;
+        XC_CASE(0) XC_CASE(1) XC_CASE(2) XC_CASE(3) XC_CASE(4) XC_CASE(5) XC_CASE(6) XC_CASE(7)
+#undef XC_CASE
+    default: break;
+    }
+}
+
+}  // namespace
+}  // namespace xc

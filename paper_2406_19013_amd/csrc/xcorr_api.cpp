@@ -16,7 +16,8 @@
 
 // Kernel family a 4+4-bit int8-MFMA context runs (the tuner times the same).
 enum class Kernel4 {
-    Fused,   // fused products: one Re and one Im accumulator per tile
+    Gauss,   // three products per tile, persistent; whole-triangle regions (default)
+    Fused,   // fused products: one Re and one Im accumulator per tile ($XCORR_MFMA4_VARIANT=fused)
     Roles,   // one wave per real product ($XCORR_MFMA4_VARIANT=roles)
 };
 
@@ -85,13 +86,26 @@ int default_tile(int N)
 Kernel4 kernel4_from_env()
 {
     const char *fv = std::getenv("XCORR_MFMA4_VARIANT");
-    return fv && std::strcmp(fv, "roles") == 0 ? Kernel4::Roles : Kernel4::Fused;
+    if (fv && std::strcmp(fv, "roles") == 0)
+        return Kernel4::Roles;
+    if (fv && std::strcmp(fv, "fused") == 0)
+        return Kernel4::Fused;
+    return Kernel4::Gauss;
 }
 
-// Name of the kernel an ingest of this config launches (batch = 0) or that
-// the batched launch runs for it (batch = 1); the tuner times that kernel and
-// labels its tune-cache line with this name.
-const char *kernel_name(const xcorr_config &c, bool batch)
+// The three-product kernel takes plans with one whole-triangle region per
+// channel and N a multiple of 16 (16-byte-aligned inputs are checked per call).
+bool gauss_runs(Kernel4 k, const xc::Plan &pl, int F, int N)
+{
+    return k == Kernel4::Gauss && xc::gauss4_supported(pl, F, N);
+}
+
+int default_tile(int N);
+
+// Name of the kernel an ingest of this config with this tile launches
+// (batch = 0) or that the batched launch runs for it (batch = 1); the tuner
+// times that kernel and labels its tune-cache line with this name.
+const char *kernel_for(const xcorr_config &c, int tile, bool batch)
 {
     if (c.path == XCORR_PATH_PLAIN)
         return "xc_plain_kernel";
@@ -99,7 +113,11 @@ const char *kernel_name(const xcorr_config &c, bool batch)
         return "xc_batch4_kernel";
     if (c.sample_bits == 8)
         return c.path == XCORR_PATH_F16_MFMA ? "xc_mfma8_kernel_f16" : "xc_mfma8_kernel_i8";
-    return kernel4_from_env() == Kernel4::Roles ? "xc_mfma4_kernel" : "xc_mfma4f_kernel";
+    const Kernel4 k = kernel4_from_env();
+    if (k == Kernel4::Roles)
+        return "xc_mfma4_kernel";
+    return gauss_runs(k, xc::make_plan(c.n_inputs, tile), c.n_chans, c.n_inputs) ? "xc_gauss4_kernel"
+                                                                                : "xc_mfma4f_kernel";
 }
 
 // Tiles the batched kernel carries for an array of N inputs.
@@ -117,7 +135,6 @@ int cached_tile(const xcorr_config &c, bool batch)
     FILE *fh = std::fopen(path, "r");
     if (!fh)
         return 0;
-    const char *want = kernel_name(c, batch);
     char line[256];
     int found = 0;
     while (std::fgets(line, sizeof line, fh)) {
@@ -126,8 +143,8 @@ int cached_tile(const xcorr_config &c, bool batch)
         if (std::sscanf(line, "%d %d %d %d %d %95s", &bits, &n, &f, &p, &tile, kern) != 6)
             continue;
         if (bits == c.sample_bits && n == c.n_inputs && f == c.n_chans && p == c.path &&
-            std::strcmp(kern, want) == 0 &&
-            (batch ? batch_tile_supported(n, tile) : xc::plan_supported(n, tile)))
+            (batch ? batch_tile_supported(n, tile) : xc::plan_supported(n, tile)) &&
+            std::strcmp(kern, kernel_for(c, tile, batch)) == 0)
             found = tile;
     }
     std::fclose(fh);
@@ -225,7 +242,92 @@ void note_ingest(xcorr_ctx *ctx, int64_t n_samples, uint64_t seq)
     ++ctx->ingests;
 }
 
+// One 4+4-bit int8-MFMA launch of the kernel family the context runs:
+// results to `out`, running sums (accumulate = 1) from acc_in (default out).
+hipError_t launch4(const xcorr_ctx *ctx, const uint8_t *v, int64_t T, int2 *out, int accumulate, hipStream_t s,
+                   const int2 *acc_in = nullptr)
+{
+    const xcorr_config &c = ctx->cfg;
+    if (gauss_runs(ctx->k4, ctx->plan, c.n_chans, c.n_inputs) && (uintptr_t)v % 16 == 0)
+        return xc::launch_gauss4(ctx->plan, v, T, c.n_chans, c.n_inputs, out, accumulate, s, acc_in);
+    return xc::launch_mfma4f(ctx->plan, v, T, c.n_chans, c.n_inputs, out, accumulate, s, acc_in);
+}
+
+// The current device must be a gfx950 GPU.
+int device_check()
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipGetDevice");
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return set_error(XCORR_E_DEVICE, std::string("device is ") + prop.gcnArchName + ", not gfx950");
+    return XCORR_OK;
+}
+
+// Fill a validated context; use_cache = false leaves the tune cache file
+// unread (the tile is the config's or the built-in choice).
+void setup_ctx(xcorr_ctx *c, const xcorr_config &cfg, int64_t tm, void *ws, size_t ws_bytes, bool use_cache)
+{
+    c->cfg = cfg;
+    c->t_max = tm;
+    c->max_dump = cfg.max_samples_per_dump ? cfg.max_samples_per_dump : tm;
+    c->kc = 64;
+    if (cfg.path != XCORR_PATH_PLAIN) {
+        int tile = cfg.tile;
+        if (!tile && use_cache) {
+            tile = cached_tile(cfg, false);
+            c->tile_from_cache = tile != 0;
+        }
+        if (!tile)
+            tile = default_tile(cfg.n_inputs);
+        c->plan = xc::make_plan(cfg.n_inputs, tile);
+        // time rows staged per LDS chunk of the per-role kernel (64 or 128; 128 for D >= 4 only)
+        const char *v = std::getenv("XCORR_CHUNK");
+        if (v && std::strcmp(v, "128") == 0 && c->plan.D >= 4 && cfg.sample_bits == 4)
+            c->kc = 128;
+        c->k4 = kernel4_from_env();
+    }
+    c->ws = ws;
+    c->ws_bytes = ws_bytes;
+}
+
 }  // namespace
+
+// One integration of n_samples through a context that lives on this stack
+// frame, with `ws` (ws_bytes) as its running-sum buffer when the integration
+// needs one: a single 4+4-bit int8-MFMA launch writes straight to d_out, any
+// other integration runs through the buffer.  Allocates nothing.
+int xc::correlate_once(const xcorr_config *cfg, void *ws, size_t ws_bytes, const void *d_volts, int64_t n_samples,
+                       void *d_out, int64_t *n_integrated, hipStream_t s)
+{
+    int64_t tm = 0;
+    int rc = validate(cfg, &tm);
+    if (rc)
+        return rc;
+    if (!d_volts || !d_out)
+        return set_error(XCORR_E_INVAL, "d_volts or d_out is NULL");
+    if (n_samples < 1)
+        return set_error(XCORR_E_INVAL, "n_samples must be >= 1");
+    if (n_samples > (cfg->max_samples_per_dump ? cfg->max_samples_per_dump : tm))
+        return set_error(XCORR_E_OVERFLOW, "integration would exceed max_samples_per_dump");
+    const bool one_launch = cfg->sample_bits == 4 && cfg->path == XCORR_PATH_I8_MFMA &&
+                            kernel4_from_env() != Kernel4::Roles && n_samples <= kMaxSamplesPerLaunch4;
+    const size_t need = round_up(acc_bytes(*cfg), 256);
+    if (!one_launch && need > ws_bytes)
+        return set_error(XCORR_E_NOMEM, "the integration needs " + std::to_string(need) +
+                                            " bytes of running sums, more than the " + std::to_string(ws_bytes) +
+                                            "-byte static scratch");
+    if ((rc = device_check()) != XCORR_OK)
+        return rc;
+    xcorr_ctx c{};
+    setup_ctx(&c, *cfg, tm, ws, ws_bytes, false);
+    return xcorr_ingest_dump(&c, d_volts, n_samples, 0, d_out, n_integrated, nullptr, s);
+}
 
 struct xcorr_batch {
     std::vector<xcorr_ctx *> ctx;
@@ -263,41 +365,12 @@ int xcorr_init(const xcorr_config *cfg, void *d_workspace, size_t ws_bytes, xcor
         return set_error(XCORR_E_NOMEM, "workspace missing or smaller than xcorr_query's size");
     if ((uintptr_t)d_workspace % 256)
         return set_error(XCORR_E_INVAL, "workspace must be 256-byte aligned");
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess)
-        return hip_fail(e, "hipGetDevice");
-    hipDeviceProp_t prop;
-    e = hipGetDeviceProperties(&prop, dev);
-    if (e != hipSuccess)
-        return hip_fail(e, "hipGetDeviceProperties");
-    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
-        return set_error(XCORR_E_DEVICE, std::string("device is ") + prop.gcnArchName + ", not gfx950");
-
+    if ((rc = device_check()) != XCORR_OK)
+        return rc;
     xcorr_ctx *c = new (std::nothrow) xcorr_ctx();
     if (!c)
         return set_error(XCORR_E_NOMEM, "host allocation failed");
-    c->cfg = *cfg;
-    c->t_max = tm;
-    c->max_dump = cfg->max_samples_per_dump ? cfg->max_samples_per_dump : tm;
-    c->kc = 64;
-    if (cfg->path != XCORR_PATH_PLAIN) {
-        int tile = cfg->tile;
-        if (!tile) {
-            tile = cached_tile(*cfg, false);
-            c->tile_from_cache = tile != 0;
-        }
-        if (!tile)
-            tile = default_tile(cfg->n_inputs);
-        c->plan = xc::make_plan(cfg->n_inputs, tile);
-        // time rows staged per LDS chunk of the per-role kernel (64 or 128; 128 for D >= 4 only)
-        const char *v = std::getenv("XCORR_CHUNK");
-        if (v && std::strcmp(v, "128") == 0 && c->plan.D >= 4 && cfg->sample_bits == 4)
-            c->kc = 128;
-        c->k4 = kernel4_from_env();
-    }
-    c->ws = d_workspace;
-    c->ws_bytes = ws_bytes;
+    setup_ctx(c, *cfg, tm, d_workspace, ws_bytes, true);
     *out = c;
     return XCORR_OK;
 }
@@ -326,10 +399,10 @@ int xcorr_ingest(xcorr_ctx *ctx, const void *d_volts, int64_t n_samples, uint64_
         hipError_t e;
         if (c.path == XCORR_PATH_PLAIN)
             e = xc::launch_plain(c.sample_bits, vp, tl, c.n_chans, c.n_inputs, acc, accumulate, s);
-        else if (c.sample_bits == 4 && ctx->k4 == Kernel4::Fused)
-            e = xc::launch_mfma4f(ctx->plan, vp, tl, c.n_chans, c.n_inputs, acc, accumulate, s);
-        else if (c.sample_bits == 4)
+        else if (c.sample_bits == 4 && ctx->k4 == Kernel4::Roles)
             e = xc::launch_mfma4(ctx->plan, ctx->kc, vp, tl, c.n_chans, c.n_inputs, acc, accumulate, s);
+        else if (c.sample_bits == 4)
+            e = launch4(ctx, vp, tl, acc, accumulate, s);
         else
             e = xc::launch_mfma8(ctx->plan, c.path == XCORR_PATH_F16_MFMA, vp, tl, c.n_chans, c.n_inputs,
                                  ctx->ws, accumulate, s);
@@ -353,7 +426,7 @@ int xcorr_ingest_dump(xcorr_ctx *ctx, const void *d_volts, int64_t n_samples, ui
     if ((uintptr_t)d_out % 16)
         return set_error(XCORR_E_INVAL, "d_out must be 16-byte aligned");
     const xcorr_config &c = ctx->cfg;
-    if (!(c.sample_bits == 4 && c.path == XCORR_PATH_I8_MFMA && ctx->k4 == Kernel4::Fused)) {
+    if (!(c.sample_bits == 4 && c.path == XCORR_PATH_I8_MFMA && ctx->k4 != Kernel4::Roles)) {
         const int rc = xcorr_ingest(ctx, d_volts, n_samples, seq, stream);
         return rc ? rc : xcorr_dump(ctx, d_out, n_integrated, n_gaps, stream);
     }
@@ -368,10 +441,9 @@ int xcorr_ingest_dump(xcorr_ctx *ctx, const void *d_volts, int64_t n_samples, ui
         const bool last = t0 + tl >= n_samples;
         // the last launch adds the running sums to its own and writes the
         // result to d_out: the integration ends without a copy
-        const hipError_t e = last ? xc::launch_mfma4f(ctx->plan, v + t0 * bytes_per_row, tl, c.n_chans,
-                                                      c.n_inputs, static_cast<int2 *>(d_out), accumulate, s, acc)
-                                  : xc::launch_mfma4f(ctx->plan, v + t0 * bytes_per_row, tl, c.n_chans,
-                                                      c.n_inputs, acc, accumulate, s);
+        const hipError_t e = last ? launch4(ctx, v + t0 * bytes_per_row, tl, static_cast<int2 *>(d_out),
+                                            accumulate, s, acc)
+                                  : launch4(ctx, v + t0 * bytes_per_row, tl, acc, accumulate, s);
         if (e != hipSuccess)
             return hip_fail(e, "kernel launch");
         ++ctx->launches;
@@ -400,7 +472,7 @@ int xcorr_ingest_blocks(xcorr_ctx *ctx, const void *const *d_blocks, int n_block
     if (block_samples > (ctx->max_dump - ctx->acc_samples) / n_blocks)
         return set_error(XCORR_E_OVERFLOW, "integration would exceed max_samples_per_dump");
     const xcorr_config &c = ctx->cfg;
-    bool fused = c.sample_bits == 4 && c.path == XCORR_PATH_I8_MFMA && ctx->k4 == Kernel4::Fused &&
+    bool fused = c.sample_bits == 4 && c.path == XCORR_PATH_I8_MFMA && ctx->k4 != Kernel4::Roles &&
                  block_samples % 64 == 0 &&
                  block_samples <= xc::kMaxSamplesPerLaunch4 && c.n_inputs % 16 == 0 &&
                  64LL * c.n_chans * c.n_inputs < (1LL << 31) - 16;
@@ -424,8 +496,11 @@ int xcorr_ingest_blocks(xcorr_ctx *ctx, const void *const *d_blocks, int n_block
             bt.p[b] = static_cast<const uint8_t *>(d_blocks[b0 + b]);
         bt.chunks_per_block = (int)(block_samples / 64);
         const int accumulate = (ctx->acc_samples > 0 || b0 > 0) ? 1 : 0;
-        const hipError_t e = xc::launch_mfma4f_blocks(ctx->plan, bt, n, c.n_chans, c.n_inputs,
-                                                      static_cast<int2 *>(ctx->ws), accumulate, s);
+        const hipError_t e = gauss_runs(ctx->k4, ctx->plan, c.n_chans, c.n_inputs)
+                                 ? xc::launch_gauss4_blocks(ctx->plan, bt, n, c.n_chans, c.n_inputs,
+                                                            static_cast<int2 *>(ctx->ws), accumulate, s)
+                                 : xc::launch_mfma4f_blocks(ctx->plan, bt, n, c.n_chans, c.n_inputs,
+                                                            static_cast<int2 *>(ctx->ws), accumulate, s);
         if (e != hipSuccess)
             return hip_fail(e, "kernel launch");
         ++ctx->launches;
@@ -653,7 +728,12 @@ int xcorr_autotune_kernel(const xcorr_config *cfg, int32_t batch, char *name, si
         return set_error(XCORR_E_INVAL, "name is NULL or empty");
     if (batch && (cfg->sample_bits != 4 || cfg->path != XCORR_PATH_I8_MFMA))
         return set_error(XCORR_E_INVAL, "the batched launch takes 4+4-bit int8-MFMA configs");
-    std::snprintf(name, len, "%s", kernel_name(*cfg, batch != 0));
+    int tile = cfg->tile;
+    if (!tile && !batch)
+        tile = cached_tile(*cfg, false);
+    if (!tile)
+        tile = default_tile(cfg->n_inputs);
+    std::snprintf(name, len, "%s", kernel_for(*cfg, tile, batch != 0));
     return XCORR_OK;
 }
 
@@ -725,7 +805,7 @@ static int append_tune_line(const xcorr_config &c, int tile, bool batch)
     if (!fh)
         return set_error(XCORR_E_INVAL, std::string("cannot append to the tune cache ") + path);
     std::fprintf(fh, "%d %d %d %d %d %s\n", c.sample_bits, c.n_inputs, c.n_chans, c.path, tile,
-                 kernel_name(c, batch));
+                 kernel_for(c, tile, batch));
     std::fclose(fh);
     return XCORR_OK;
 }
@@ -807,6 +887,9 @@ static int autotune_impl(const xcorr_config *cfg, void *d_scratch, size_t scratc
             if (k4 == Kernel4::Roles)
                 return xc::launch_mfma4(pl, 64, volts, T, c.n_chans, c.n_inputs, static_cast<int2 *>(acc),
                                         accumulate, s);
+            if (gauss_runs(k4, pl, c.n_chans, c.n_inputs))
+                return xc::launch_gauss4(pl, volts, T, c.n_chans, c.n_inputs, static_cast<int2 *>(acc), accumulate,
+                                         s);
             return xc::launch_mfma4f(pl, volts, T, c.n_chans, c.n_inputs, static_cast<int2 *>(acc), accumulate, s);
         };
         float ms = 0.f;

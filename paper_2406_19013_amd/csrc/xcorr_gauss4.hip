@@ -1,0 +1,108 @@
+// 4+4-bit int8-MFMA kernels of the X-engine, three-product variant (see
+// xc_gauss4.h): one persistent work-group per CU (two for D <= 3) walks its
+// channels as one continuous stream of LDS-DMA chunks; every region is the
+// whole triangle of a channel (N <= 192).
+#include "xc_gauss4.h"
+
+namespace xc {
+namespace {
+
+template <int D, int ACC, int MB>
+__global__ __launch_bounds__(kG3Threads)
+__attribute__((amdgpu_waves_per_eu(g3_waves_per_eu(D), g3_waves_per_eu(D))))
+void xc_gauss4_kernel(const G3Args a, const BlockTable bt)
+{
+    __shared__ __attribute__((aligned(1024))) uint8_t smem[g3_smem_bytes(D)];
+    g3_dispatch<D, ACC, MB>(smem, a, &bt);
+}
+
+// compute units of the current device (queried once per device)
+int device_cu_count()
+{
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return 256;
+    if (!cached[dev]) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 8)
+            cus = 256;
+        cached[dev] = cus;
+    }
+    return cached[dev];
+}
+
+template <int D>
+hipError_t launch_t(const G3Args &a, const BlockTable *bt, int accumulate, hipStream_t s)
+{
+    const int per = (a.F + 7) / 8;
+    const int m_max = device_cu_count() * g3_wgs_per_cu(D) / 8;
+    const int grid = 8 * std::max(1, std::min(m_max, per));
+    G3Args args = a;
+    args.per = per;
+    BlockTable table{};
+    if (bt)
+        table = *bt;
+    auto kern = bt ? (accumulate ? xc_gauss4_kernel<D, 1, 1> : xc_gauss4_kernel<D, 0, 1>)
+                   : (accumulate ? xc_gauss4_kernel<D, 1, 0> : xc_gauss4_kernel<D, 0, 0>);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kG3Threads), 0, s, args, table);
+    return hipGetLastError();
+}
+
+hipError_t launch_any(int D, const G3Args &a, const BlockTable *bt, int accumulate, hipStream_t s)
+{
+    switch (D) {
+    case 1: return launch_t<1>(a, bt, accumulate, s);
+    case 2: return launch_t<2>(a, bt, accumulate, s);
+    case 3: return launch_t<3>(a, bt, accumulate, s);
+    case 4: return launch_t<4>(a, bt, accumulate, s);
+    case 5: return launch_t<5>(a, bt, accumulate, s);
+    case 6: return launch_t<6>(a, bt, accumulate, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+bool gauss4_supported(const Plan &pl, int F, int N)
+{
+    return pl.nseg == 1 && pl.regions == 1 && pl.D >= 1 && pl.D <= 6 && N <= 32 * pl.D && N % 16 == 0 &&
+           F >= 1 && 64LL * F * N < (1LL << 31) - 16;
+}
+
+hipError_t launch_gauss4(const Plan &pl, const uint8_t *volts, int64_t T, int F, int N, int2 *acc, int accumulate,
+                         hipStream_t s, const int2 *acc_in)
+{
+    if (!gauss4_supported(pl, F, N) || T < 1 || T > kMaxSamplesPerLaunch4 || !volts || (uintptr_t)volts % 16 ||
+        !acc)
+        return hipErrorInvalidValue;
+    G3Args a{};
+    a.volts = volts;
+    a.T = T;
+    a.F = F;
+    a.N = N;
+    a.out = acc;
+    a.in = acc_in ? acc_in : acc;
+    return launch_any(pl.D, a, nullptr, accumulate, s);
+}
+
+hipError_t launch_gauss4_blocks(const Plan &pl, const BlockTable &bt, int n_blocks, int F, int N, int2 *acc,
+                                int accumulate, hipStream_t s, const int2 *acc_in)
+{
+    if (!gauss4_supported(pl, F, N) || n_blocks < 1 || n_blocks > kMaxFusedBlocks || bt.chunks_per_block < 1 ||
+        (int64_t)n_blocks * bt.chunks_per_block * 64 > kMaxSamplesPerLaunch4 || !acc)
+        return hipErrorInvalidValue;
+    for (int b = 0; b < n_blocks; ++b)
+        if (!bt.p[b] || (uintptr_t)bt.p[b] % 16)
+            return hipErrorInvalidValue;
+    G3Args a{};
+    a.volts = bt.p[0];
+    a.T = (int64_t)n_blocks * bt.chunks_per_block * 64;
+    a.F = F;
+    a.N = N;
+    a.out = acc;
+    a.in = acc_in ? acc_in : acc;
+    return launch_any(pl.D, a, &bt, accumulate, s);
+}
+
+}  // namespace xc

@@ -1,6 +1,7 @@
 // Internal declarations shared by the host API and the kernel launchers.
 #pragma once
 #include <hip/hip_runtime.h>
+#include "xcorr.h"
 #include <cstdint>
 #include <string>
 
@@ -30,6 +31,12 @@ CtxShape ctx_shape(const xcorr_ctx *ctx);
 
 Plan make_plan(int N, int D);
 bool plan_supported(int N, int D);
+
+// One integration through a stack-held context whose running sums (when the
+// integration needs any) are `ws`; allocates nothing (the static-scratch
+// entry point).
+int correlate_once(const xcorr_config *cfg, void *ws, size_t ws_bytes, const void *d_volts, int64_t n_samples,
+                   void *d_out, int64_t *n_integrated, hipStream_t s);
 
 // Launchers: enqueue on `stream`, return hipSuccess or the launch error.
 // `accumulate` = 0 overwrites the accumulators, 1 adds to them.
@@ -79,6 +86,15 @@ struct BlockTable {
     int chunks_per_block;
 };
 hipError_t launch_mfma4f_blocks(const Plan &pl, const BlockTable &bt, int n_blocks, int F, int N, int2 *acc,
+                                int accumulate, hipStream_t s, const int2 *acc_in = nullptr);
+
+// Three-product kernel (4+4-bit, int8 MFMA): persistent, one whole-triangle
+// region per channel (N <= 32 D, D <= 6), N a multiple of 16, 16-byte-aligned
+// input.  acc_in as for launch_mfma4f.
+bool gauss4_supported(const Plan &pl, int F, int N);
+hipError_t launch_gauss4(const Plan &pl, const uint8_t *volts, int64_t T, int F, int N, int2 *acc, int accumulate,
+                         hipStream_t s, const int2 *acc_in = nullptr);
+hipError_t launch_gauss4_blocks(const Plan &pl, const BlockTable &bt, int n_blocks, int F, int N, int2 *acc,
                                 int accumulate, hipStream_t s, const int2 *acc_in = nullptr);
 
 // Batched persistent launch (4+4-bit, int8 MFMA): one kernel drains a work

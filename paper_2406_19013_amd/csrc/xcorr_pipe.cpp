@@ -101,18 +101,27 @@ void destroy_events(xcorr_pipe *p)
     p->spare.clear();
 }
 
-// Set the clock anchor (the compute stream must be idle: after a drain).
+// Set the clock anchor: record an event on the compute stream and wait for
+// it; the event ran between the host times before the record and after the
+// wait.  Work queued ahead of it (on this stream, or on another stream that
+// shares its hardware queue) widens that window, so the anchor is taken
+// again, up to 8 times, until the window is below 200 us; the event keeps
+// the last recording, whose window is used and whose half-width is reported.
 int set_anchor(xcorr_pipe *p)
 {
     hipError_t e = hipSuccess;
     if (!p->anchor)
         e = hipEventCreate(&p->anchor);
-    const double a = host_now_s();
-    if (e == hipSuccess)
+    double a = 0.0, b = 0.0;
+    for (int k = 0; k < 8 && e == hipSuccess; ++k) {
+        a = host_now_s();
         e = hipEventRecord(p->anchor, p->compute);
-    if (e == hipSuccess)
-        e = hipEventSynchronize(p->anchor);
-    const double b = host_now_s();
+        if (e == hipSuccess)
+            e = hipEventSynchronize(p->anchor);
+        b = host_now_s();
+        if (b - a < 200e-6)
+            break;
+    }
     if (e != hipSuccess)
         return hip_err(e, "clock anchor event");
     p->anchor_s = 0.5 * (a + b);

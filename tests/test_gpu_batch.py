@@ -186,12 +186,14 @@ def test_batch_rejects_mixed_paths():
 def test_autotune_picks_supported_tile_and_caches(tmp_path, monkeypatch, bits, path, N, F):
     cache = tmp_path / "tune.txt"
     monkeypatch.setenv("XCORR_TUNE_CACHE", str(cache))
+    monkeypatch.delenv("XCORR_MFMA4_VARIANT", raising=False)
     best = X.autotune(N, F, bits, path)
     assert 1 <= best <= 6
     lines = cache.read_text().split("\n")
-    assert lines[0].split() == [str(bits), str(N), str(F), str(path), str(best)]
+    kernel = X.xcorr_autotune_kernel(X.make_config(N, F, bits, path))
+    assert lines[0].split() == [str(bits), str(N), str(F), str(path), str(best), kernel]
     c = X.Correlator(N, F, bits, path)
-    assert c.stats()["tile"] == best
+    assert c.stats()["tile"] == best and c.stats()["tile_from_cache"] == 1
     v = (synth.uniform_volts4(N, F, 70, seed=(3006,)) if bits == 4
          else synth.uniform_volts8(N, F, 70, seed=(3006,)))
     c.ingest(v.cuda())
@@ -201,4 +203,30 @@ def test_autotune_picks_supported_tile_and_caches(tmp_path, monkeypatch, bits, p
         assert np.array_equal(got.cpu().numpy().astype(np.int64), exp)
     else:
         assert np.array_equal(got.cpu().numpy(), oracle.to_int32(exp))
+    c.close()
+
+
+def test_batch_autotune_times_the_batched_kernel_and_batch_uses_it(tmp_path, monkeypatch):
+    """The batch tuner times the persistent kernel over the tiles it carries
+    and writes an xc_batch4_kernel line; a batch built afterwards takes that
+    tile for the member (the member's own single-array tile is separate) and
+    stays exact."""
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("XCORR_TUNE_CACHE", str(cache))
+    N, F, T = 256, 32, 130
+    best = X.autotune(N, F, 4, X.PATH_I8_MFMA, batch=True)
+    assert best in (2, 3, 4)
+    assert cache.read_text().split() == ["4", str(N), str(F), "1", str(best), "xc_batch4_kernel"]
+    cfg = X.make_config(N, F, 4, X.PATH_I8_MFMA)
+    assert X.xcorr_plan_tile(cfg, batch=True) == (best, True)
+    assert X.xcorr_plan_tile(cfg) == (4, False)          # no line for the single-array kernel
+    c = X.Correlator(N, F, 4, X.PATH_I8_MFMA)
+    b = X.Batch([c])
+    assert b.tiles == [best]
+    v = synth.uniform_volts4(N, F, T, seed=(3007,))
+    b.ingest([v.cuda()])
+    got, n, _ = c.dump()
+    torch.cuda.synchronize()
+    assert n == T and np.array_equal(got.cpu().numpy(), want(v, N, F))
+    b.close()
     c.close()
