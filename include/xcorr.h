@@ -372,6 +372,28 @@ int xcorr_reorder_flush(xcorr_reorder *r, int32_t to_boundary, xcorr_event *even
 int xcorr_reorder_stats(const xcorr_reorder *r, xcorr_reorder_stats_t *out);
 int xcorr_reorder_destroy(xcorr_reorder *r);
 
+/*
+ * One integration without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): as a context created from *cfg with tile = the
+ * config's (0: the built-in choice; the tune cache is not read), followed by
+ * one xcorr_ingest_dump(n_samples) into d_out, with no context, no workspace
+ * and no allocation.  An integration that needs running sums (more samples
+ * than one 4+4-bit int8-MFMA launch takes, 130,560, or any 8+8-bit or plain
+ * integration) keeps them in a library-held device array of
+ * XCORR_STATIC_SCRATCH_BYTES per GPU, held until the process ends; configs
+ * whose sums (F*P*2*4 bytes, rounded up to 256) exceed it are refused with
+ * XCORR_E_NOMEM before anything is enqueued.  The first launch of an
+ * integration overwrites the array, so nothing needs clearing; it keeps the
+ * last call's contents.  Calls that overlap on one GPU (two streams, or two
+ * host threads) share the array and race.  Errors: as xcorr_query and
+ * xcorr_ingest_dump, XCORR_E_NOMEM as above, XCORR_E_HIP if the array's
+ * address cannot be looked up.
+ */
+#define XCORR_STATIC_SCRATCH_BYTES (16u << 20)
+int xcorr_correlate_static(const xcorr_config *cfg, const void *d_volts, int64_t n_samples, void *d_out,
+                           int64_t *n_integrated, void *stream);
+
 const char *xcorr_strerror(int code);
 /* Detail of the last XCORR_E_HIP / XCORR_E_DEVICE on this thread. */
 const char *xcorr_last_error(void);

@@ -151,6 +151,7 @@ def load(path: str | None = None):
             "xcorr_autotune_kernel": [cfgp, ctypes.c_int32, ctypes.c_char_p, sz],
             "xcorr_plan_tile": [cfgp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                 ctypes.POINTER(ctypes.c_int32)],
+            "xcorr_correlate_static": [cfgp, vp, i64, vp, ctypes.POINTER(i64), vp],
             "xcorr_pipe_query": [vp, ctypes.c_int, i64, ctypes.POINTER(sz)],
             "xcorr_pipe_init": [vp, ctypes.c_int, i64, i64, vp, sz, vp, vp, ctypes.POINTER(vp)],
             "xcorr_pipe_push": [vp, vp, ctypes.c_int, u64, vp, ctypes.POINTER(ctypes.c_int)],
@@ -454,6 +455,19 @@ def xcorr_admit(cfgs, block_samples, n_slots, budget_bytes: int):
     used = ctypes.c_size_t()
     _check(load().xcorr_admit(arr, n, bs, sl, int(budget_bytes), adm, ctypes.byref(used)), "xcorr_admit")
     return [bool(a) for a in adm], used.value
+
+
+STATIC_SCRATCH_BYTES = 16 << 20
+
+
+def xcorr_correlate_static(cfg: Config, volts, n_samples: int, out, stream=None) -> int:
+    """One integration into `out` without any allocation (running sums in the
+    library's static device array); returns the samples integrated."""
+    n = ctypes.c_int64()
+    _check(load().xcorr_correlate_static(ctypes.byref(cfg), ctypes.c_void_p(volts.data_ptr()), int(n_samples),
+                                         ctypes.c_void_p(out.data_ptr()), ctypes.byref(n), _stream_handle(stream)),
+           "xcorr_correlate_static")
+    return n.value
 
 
 def xcorr_strerror(code: int) -> str:
