@@ -20,16 +20,23 @@
 // the combinations are evaluated in wrapping 32-bit arithmetic, whose result
 // is exact because the true values (32 Im, 2 II) fit in int32.
 //
+// The per-input sums come from unsigned byte SADs, which issue beside the
+// MFMAs (a dot-product instruction would share their pipe): with Z = x ^ 0x88
+// (both nibbles offset by 8, so the unsigned byte is 16 (re + 8) + im + 8)
+// and |A - R| = im + 8 per byte (A and R share the high nibble),
+//     SA = sum Z - 128 Tp,   SR = sum Z - sum |A - R| - 128 Tp.
+//
 // Work split.  One work-group per channel region (here: the whole triangle of
 // D 32-input blocks, D <= 6), persistent: each work-group walks its channels
 // as one continuous stream of 64-sample chunks through an LDS ring, so the
 // next channel's first chunks are in flight while the current channel's
-// results are stored.  The triangle's tiles, in row-major order, are cut into
-// 8 contiguous segments of near-equal MFMA count, one per wave, and the
-// segments are placed so that the two waves sharing a SIMD carry
-// complementary loads.  A wave owns every product of its tiles, combines them
-// in registers and stores the visibilities directly (no staging), except the
-// transposed P_ab of a diagonal tile, which goes through a small LDS tile.
+// results are stored.  The triangle's tiles are split over 8 waves (two per
+// SIMD) so that every SIMD carries near-equal MFMA work and the waves unpack
+// as few blocks per K step as possible (a block's three forms are computed by
+// every wave that reads it).  A wave owns every product of its tiles,
+// combines them in registers and stores the visibilities directly (no
+// staging), except the transposed P_ab of a diagonal tile, which goes through
+// a small LDS tile.
 #pragma once
 #include "xc_mfma4.h"
 
@@ -42,44 +49,43 @@ constexpr int g3_ntiles(int D) { return D * (D + 1) / 2; }
 constexpr bool g3_diag(int t) { return tri_I(t) == tri_J(t); }
 constexpr int g3_abs(int x) { return x < 0 ? -x : x; }
 
-// Waves per work-group.  Four (one per SIMD, 512 registers each) keep the
-// accumulators in AGPRs and give every wave a long run of independent MFMAs
-// under which it unpacks the next step's operands.
+// Waves per work-group: two per SIMD, 256 registers each.
 #ifndef XC_G3_WAVES
 #define XC_G3_WAVES 8
 #endif
 constexpr int kG3Waves = XC_G3_WAVES;
 constexpr int kG3Threads = 64 * kG3Waves;
 
-// The split, evaluated once per D: wave slot s takes tiles [t0[s], t1[s]).
-// Tiles in row-major order are cut into W contiguous segments at the
-// boundaries whose cumulative MFMA count (3 per off-diagonal tile, 2 per
-// diagonal tile) is closest to k/W of the total.  With 8 waves (two per
-// SIMD) the four largest segments take slots 0..3 and the others slots
-// 7..4, so that slot s and slot s + 4 pair the r-th largest segment with the
-// r-th smallest; with 4 waves slot s takes segment s.
+// The split, evaluated once per D: wave slot s (on SIMD s % 4) takes the
+// tiles whose bits are set in mask[s] (bit t: tile t in row-major order).
+constexpr int kG3MaxWaves = 16;
 struct G3Split {
-    int t0[8], t1[8];
-    int units[8];
+    uint32_t mask[kG3MaxWaves];
     int sum_owner[6];   // wave slot that sums the forms of block b
 };
-constexpr G3Split g3_make_split(int D, int W)
+constexpr int g3_units(int t) { return g3_diag(t) ? 2 : 3; }
+constexpr bool g3_touches(uint32_t mask, int b)
+{
+    for (int t = 0; t < 21; ++t)
+        if ((mask >> t & 1) && (tri_I(t) == b || tri_J(t) == b))
+            return true;
+    return false;
+}
+
+// Generic split: tiles in row-major order are cut into W contiguous segments
+// at the boundaries whose cumulative MFMA count (3 per off-diagonal tile, 2
+// per diagonal tile) is closest to k/W of the total; segments go to SIMDs
+// largest first, each to the SIMD with the least MFMA work so far; the sums
+// of a block go to the least-loaded wave that reads it.
+constexpr G3Split g3_contiguous_split(int D, int W)
 {
     G3Split sp{};
     const int NT = g3_ntiles(D);
     int cum[6 * 7 / 2 + 1] = {};
-    int row = 0, col = 0;
-    for (int t = 0; t < NT; ++t) {
-        cum[t + 1] = cum[t] + (row == col ? 2 : 3);
-        if (col == row) {
-            ++row;
-            col = 0;
-        } else {
-            ++col;
-        }
-    }
+    for (int t = 0; t < NT; ++t)
+        cum[t + 1] = cum[t] + g3_units(t);
     const int U = cum[NT];
-    int bound[9] = {};
+    int bound[kG3MaxWaves + 1] = {};
     for (int k = 1; k < W; ++k) {
         int best = 0;
         for (int b = 0; b <= NT; ++b)
@@ -88,87 +94,114 @@ constexpr G3Split g3_make_split(int D, int W)
         bound[k] = best;
     }
     bound[W] = NT;
-    int su[8] = {};
+    int su[kG3MaxWaves] = {};
     for (int k = 0; k < W; ++k)
         su[k] = cum[bound[k + 1]] - cum[bound[k]];
-    for (int k = 0; k < W; ++k) {
-        int slot = k;
-        if (W == 8) {
-            int r = 0;
-            for (int m = 0; m < 8; ++m)
-                if (su[m] > su[k] || (su[m] == su[k] && m < k))
-                    ++r;
-            slot = r < 4 ? r : 4 + (7 - r);
-        }
-        sp.t0[slot] = bound[k];
-        sp.t1[slot] = bound[k + 1];
-        sp.units[slot] = su[k];
+    bool placed[kG3MaxWaves] = {};
+    int simd_load[4] = {}, simd_used[4] = {}, units[kG3MaxWaves] = {};
+    for (int n = 0; n < W; ++n) {
+        int k = -1;
+        for (int m = 0; m < W; ++m)
+            if (!placed[m] && (k < 0 || su[m] > su[k]))
+                k = m;
+        int simd = 0;
+        for (int q = 1; q < 4; ++q)
+            if (simd_used[q] < W / 4 && (simd_used[simd] >= W / 4 || simd_load[q] < simd_load[simd]))
+                simd = q;
+        const int slot = simd + 4 * simd_used[simd];
+        placed[k] = true;
+        simd_load[simd] += su[k];
+        ++simd_used[simd];
+        for (int t = bound[k]; t < bound[k + 1]; ++t)
+            sp.mask[slot] |= 1u << t;
+        units[slot] = su[k];
     }
-    // the per-block sums go to the wave, among those that read the block,
-    // with the least work so far (MFMA units plus 3 per block already summed)
-    int load[8] = {};
-    for (int s = 0; s < W; ++s)
-        load[s] = sp.units[s];
     for (int b = 0; b < D; ++b) {
         int best = -1;
-        for (int s = 0; s < W; ++s) {
-            bool uses = false;
-            int r = 0, c = 0;
-            for (int t = 0; t < NT; ++t) {
-                if (t >= sp.t0[s] && t < sp.t1[s] && (r == b || c == b))
-                    uses = true;
-                if (c == r) {
-                    ++r;
-                    c = 0;
-                } else {
-                    ++c;
-                }
-            }
-            if (uses && (best < 0 || load[s] < load[best]))
+        for (int s = 0; s < W; ++s)
+            if (g3_touches(sp.mask[s], b) && (best < 0 || units[s] < units[best]))
                 best = s;
-        }
         sp.sum_owner[b] = best;
         if (best >= 0)
-            load[best] += 3;
+            units[best] += 3;
     }
     return sp;
+}
+
+// Searched splits for 8 waves and D = 5, 6: per SIMD the MFMA counts are as
+// even as the tile sizes allow, each wave holds 5 to 9 MFMA accumulators, and
+// the number of blocks that waves unpack per K step is the smallest found
+// (D = 6: 20 instead of 25 for contiguous segments; D = 5: 18 instead of 20).
+//   D = 6: slot 0 {(1,1) (4,1)}  1 {(2,2) (4,2)}  2 {(4,3) (5,3) (5,4)}
+//          3 {(0,0) (4,0) (4,4)}  4 {(2,0) (5,0) (5,2)}  5 {(1,0) (3,0) (3,1)}
+//          6 {(5,1) (5,5)}  7 {(2,1) (3,2) (3,3)}
+//   D = 5: slot 0 {(4,2)}  1 {(4,3) (4,4)}  2 {(1,0) (1,1)}  3 {(0,0) (4,0)}
+//          4 {(3,0) (3,3)}  5 {(2,2) (3,2)}  6 {(2,0) (2,1)}  7 {(3,1) (4,1)}
+constexpr G3Split g3_make_split(int D, int W)
+{
+    if (W == 8 && D == 6)
+        return G3Split{{0x804, 0x1020, 0xc2000, 0x4401, 0x28008, 0xc2, 0x110000, 0x310}, {3, 0, 1, 2, 0, 6}};
+    if (W == 8 && D == 5)
+        return G3Split{{0x1000, 0x6000, 0x6, 0x401, 0x240, 0x120, 0x18, 0x880}, {4, 2, 5, 1, 0, -1}};
+    return g3_contiguous_split(D, W);
 }
 template <int D>
 constexpr G3Split kG3Split = g3_make_split(D, kG3Waves);
 
 template <int D>
-constexpr int g3_t0(int s) { return kG3Split<D>.t0[s]; }
+constexpr uint32_t g3_mask(int s) { return kG3Split<D>.mask[s]; }
 template <int D>
-constexpr int g3_t1(int s) { return kG3Split<D>.t1[s]; }
+constexpr bool g3_has(int s, int t) { return t < 32 && (g3_mask<D>(s) >> t & 1); }
+// position of tile t among the tiles of slot s (its accumulator index)
 template <int D>
-constexpr bool g3_uses_block(int s, int b)
+constexpr int g3_rank(int s, int t)
 {
-    for (int t = g3_t0<D>(s); t < g3_t1<D>(s); ++t)
-        if (tri_I(t) == b || tri_J(t) == b)
-            return true;
-    return false;
+    int r = 0;
+    for (int u = 0; u < t; ++u)
+        r += g3_has<D>(s, u);
+    return r;
 }
+template <int D>
+constexpr int g3_ntiles_of(int s) { return g3_rank<D>(s, g3_ntiles(D)); }
+template <int D>
+constexpr bool g3_uses_block(int s, int b) { return g3_touches(g3_mask<D>(s), b); }
 template <int D>
 constexpr bool g3_owns_sums(int s, int b)
 {
     return kG3Split<D>.sum_owner[b] == s;
 }
-// Order in which a wave unpacks its blocks within a K step: the row block of
-// its first tile first (shared by most of its tiles), then the others in
-// increasing order.  pos < 0 for a block the wave does not read.
+// Order in which a wave unpacks its blocks within a K step: greedily the
+// block that completes the most MFMA work with the blocks already unpacked
+// (ties: the lower block), so that MFMAs start early and the later blocks'
+// unpacking runs under them.  pos < 0 for a block the wave does not read.
 template <int D>
 constexpr int g3_block_pos(int s, int b)
 {
     if (!g3_uses_block<D>(s, b))
         return -1;
-    const int first = g3_t0<D>(s) < g3_t1<D>(s) ? tri_I(g3_t0<D>(s)) : 0;
-    if (b == first)
-        return 0;
-    int p = 1;
-    for (int c = 0; c < b; ++c)
-        if (c != first && g3_uses_block<D>(s, c))
-            ++p;
-    return p;
+    bool done[6] = {};
+    for (int p = 0; p < D; ++p) {
+        int best = -1, best_gain = -1;
+        for (int c = 0; c < D; ++c) {
+            if (done[c] || !g3_uses_block<D>(s, c))
+                continue;
+            int gain = 0;
+            for (int t = 0; t < g3_ntiles(D); ++t)
+                if (g3_has<D>(s, t) && (tri_I(t) == c || tri_J(t) == c)) {
+                    const int o = tri_I(t) == c ? tri_J(t) : tri_I(t);
+                    if (o == c || done[o])
+                        gain += g3_units(t);
+                }
+            if (gain > best_gain) {
+                best = c;
+                best_gain = gain;
+            }
+        }
+        if (best == b)
+            return p;
+        done[best] = true;
+    }
+    return -1;
 }
 // a tile's MFMAs go right after the later of its two blocks is unpacked
 template <int D>
@@ -181,8 +214,9 @@ template <int D>
 constexpr int g3_mfmas_of(int s)
 {
     int n = 0;
-    for (int t = g3_t0<D>(s); t < g3_t1<D>(s); ++t)
-        n += g3_diag(t) ? 2 : 3;
+    for (int t = 0; t < g3_ntiles(D); ++t)
+        if (g3_has<D>(s, t))
+            n += g3_units(t);
     return n;
 }
 
@@ -238,8 +272,8 @@ __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const Bl
     constexpr int KC = kG3Chunk;
     constexpr int BUF = KC * kRowBytes;
     constexpr int LOADS = KC * 16 / kG3Threads;         // 16-byte DMA units per lane per chunk
-    constexpr int T0 = g3_t0<D>(SLOT), T1 = g3_t1<D>(SLOT);
-    constexpr int NT = T1 > T0 ? T1 - T0 : 1;
+    constexpr int NTT = g3_ntiles(D);
+    constexpr int NT = g3_ntiles_of<D>(SLOT) > 0 ? g3_ntiles_of<D>(SLOT) : 1;
 
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
@@ -324,7 +358,10 @@ __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const Bl
     };
 
     v16i acc_ab[NT], acc_ba[NT], acc_rr[NT];
-    int sr[D], sa[D], sr2[D], sa2[D];
+    // per-input sums of the owned blocks, as unsigned byte SADs (two chains
+    // each): sz = sum of X ^ 0x88 (16 (re + 8) + im + 8 per sample), sl =
+    // sum of |A - R| (im + 8 per sample: A and R share the high nibble)
+    int sz[D], sl[D], sz2[D], sl2[D];
     auto clear = [&]() {
         static_for<0, NT>([&](auto tc) {
             acc_ab[tc] = v16i{};
@@ -332,10 +369,10 @@ __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const Bl
             acc_rr[tc] = v16i{};
         });
         static_for<0, D>([&](auto bc) {
-            sr[bc] = 0;
-            sa[bc] = 0;
-            sr2[bc] = 0;
-            sa2[bc] = 0;
+            sz[bc] = 0;
+            sl[bc] = 0;
+            sz2[bc] = 0;
+            sl2[bc] = 0;
         });
     };
     clear();
@@ -351,51 +388,21 @@ __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const Bl
                 X[b] = frag_tr8<8 * kRowBytes>(cb + colo[b] + koff);
         });
     };
-    auto unpack = [&](const v4i *X, v4i *A, v4i *B, v4i *R) {
-        static_for<0, D>([&](auto bc) {
-            constexpr int b = bc;
-            if constexpr (g3_uses_block<D>(SLOT, b)) {
-                A[b] = X[b] ^ 0x08080808;
-                B[b] = X[b] ^ 0x07070707;
-                R[b] = X[b] & (int)0xF0F0F0F0;
-                if constexpr (g3_owns_sums<D>(SLOT, b)) {
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        sr[b] = __builtin_amdgcn_sdot4(R[b][k], 0x01010101, sr[b], false);
-                        sa[b] = __builtin_amdgcn_sdot4(A[b][k], 0x01010101, sa[b], false);
-                    }
-                }
-            }
-        });
-    };
-    // the step's MFMAs, independent accumulators back to back
-    auto mfmas = [&](const v4i *A, const v4i *B, const v4i *R) {
-        static_for<T0, T1>([&](auto tc) {
-            constexpr int t = tc;
-            acc_ab[t - T0] = mfma_i8(A[tri_I(t)], B[tri_J(t)], acc_ab[t - T0]);
-        });
-        static_for<T0, T1>([&](auto tc) {
-            constexpr int t = tc;
-            if constexpr (!g3_diag(t))
-                acc_ba[t - T0] = mfma_i8(B[tri_I(t)], A[tri_J(t)], acc_ba[t - T0]);
-        });
-        static_for<T0, T1>([&](auto tc) {
-            constexpr int t = tc;
-            acc_rr[t - T0] = mfma_i8(R[tri_I(t)], R[tri_J(t)], acc_rr[t - T0]);
-        });
-    };
-
     // epilogue of one channel: combine, descale and store this wave's tiles
     auto epilogue = [&](int f) {
         // per-input sums: lanes l and l + 32 hold the two K halves of input l % 32
         static_for<0, D>([&](auto bc) {
             constexpr int b = bc;
             if constexpr (g3_owns_sums<D>(SLOT, b)) {
-                const int srl = sr[b] + sr2[b], sal = sa[b] + sa2[b];
-                const int srt = srl + __shfl_xor(srl, 32);
-                const int sat = sal + __shfl_xor(sal, 32);
+                const int szl = sz[b] + sz2[b], sll = sl[b] + sl2[b];
+                const uint32_t szt = (uint32_t)(szl + __shfl_xor(szl, 32));
+                const uint32_t slt = (uint32_t)(sll + __shfl_xor(sll, 32));
+                // g = 16 SR - 15 SA and h = 16 SR - SA, with SR = sum R =
+                // szt - slt - 128 Tp and SA = sum A = szt - 128 Tp
                 if (lane < 32)
-                    *(int2 *)&gh[(b * 32 + lane) * 2] = make_int2(16 * srt - 15 * sat, 16 * srt - sat);
+                    *(int2 *)&gh[(b * 32 + lane) * 2] =
+                        make_int2((int)(szt - 16u * slt - 128u * (uint32_t)Tp),
+                                  (int)(15u * szt - 16u * slt - 1920u * (uint32_t)Tp));
             }
         });
         wait_lgkm0();
@@ -405,8 +412,10 @@ __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const Bl
         const int2 *const in_f = a.in + (int64_t)f * P;
         const int jl = lane & 31;
         const int il0 = 4 * (lane >> 5);
-        static_for<T0, T1>([&](auto tc) {
+        static_for<0, NTT>([&](auto tc) {
             constexpr int t = tc;
+            if constexpr (g3_has<D>(SLOT, t)) {
+            constexpr int q = g3_rank<D>(SLOT, t);
             constexpr int I = tri_I(t), J = tri_J(t);
             constexpr bool diag = g3_diag(t);
             const int j = J * 32 + jl;
@@ -417,12 +426,12 @@ __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const Bl
                 int *const tr = trs + g3_diag_slot(t) * 32 * kG3TileStride;
 #pragma unroll
                 for (int r = 0; r < 16; ++r)
-                    tr[(8 * (r >> 2) + il0 + (r & 3)) * kG3TileStride + jl] = acc_ab[t - T0][r];
+                    tr[(8 * (r >> 2) + il0 + (r & 3)) * kG3TileStride + jl] = acc_ab[q][r];
 #pragma unroll
                 for (int r = 0; r < 16; ++r)
                     ba[r] = tr[jl * kG3TileStride + 8 * (r >> 2) + il0 + (r & 3)];
             } else {
-                ba = acc_ba[t - T0];
+                ba = acc_ba[q];
             }
 #pragma unroll
             for (int r4 = 0; r4 < 4; ++r4) {
@@ -446,11 +455,11 @@ __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const Bl
                 for (int u = 0; u < 4; ++u) {
                     const int r = 4 * r4 + u;
                     const int i = ib + u;
-                    const uint32_t ab = (uint32_t)acc_ab[t - T0][r], bav = (uint32_t)ba[r];
-                    const uint32_t rr = (uint32_t)acc_rr[t - T0][r];
+                    const uint32_t ab = (uint32_t)acc_ab[q][r], bav = (uint32_t)ba[r];
+                    const uint32_t rr = (uint32_t)acc_rr[q][r];
                     const int im = (int)(ab - bav + (uint32_t)gi[u] - (uint32_t)ghj.x) >> 5;
                     const int ii = (int)(2u * rr - ab - bav + (uint32_t)hi[u] + (uint32_t)ghj.y + 128u * (uint32_t)Tp) >> 1;
-                    int re = (acc_rr[t - T0][r] >> 8) + ii;
+                    int re = (acc_rr[q][r] >> 8) + ii;
                     int imv = im;
                     if constexpr (ACC) {
                         re += old[u].x;
@@ -459,6 +468,7 @@ __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const Bl
                     if (i < a.N && (!diag || j <= i))
                         out_f[(int64_t)i * (i + 1) / 2 + j] = make_int2(re, imv);
                 }
+            }
             }
         });
     };
@@ -496,25 +506,24 @@ __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const Bl
                     B[b] = X[b] ^ 0x07070707;
                     R[b] = X[b] & (int)0xF0F0F0F0;
                     if constexpr (g3_owns_sums<D>(SLOT, b)) {
-                        // four short chains instead of two long ones
-                        sr[b] = __builtin_amdgcn_sdot4(R[b][0], 0x01010101, sr[b], false);
-                        sa[b] = __builtin_amdgcn_sdot4(A[b][0], 0x01010101, sa[b], false);
-                        sr2[b] = __builtin_amdgcn_sdot4(R[b][1], 0x01010101, sr2[b], false);
-                        sa2[b] = __builtin_amdgcn_sdot4(A[b][1], 0x01010101, sa2[b], false);
-                        sr[b] = __builtin_amdgcn_sdot4(R[b][2], 0x01010101, sr[b], false);
-                        sa[b] = __builtin_amdgcn_sdot4(A[b][2], 0x01010101, sa[b], false);
-                        sr2[b] = __builtin_amdgcn_sdot4(R[b][3], 0x01010101, sr2[b], false);
-                        sa2[b] = __builtin_amdgcn_sdot4(A[b][3], 0x01010101, sa2[b], false);
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            int &z = k & 1 ? sz2[b] : sz[b];
+                            int &l = k & 1 ? sl2[b] : sl[b];
+                            z = (int)__builtin_amdgcn_sad_u8((uint32_t)(A[b][k] ^ (int)0x80808080), 0u, (uint32_t)z);
+                            l = (int)__builtin_amdgcn_sad_u8((uint32_t)A[b][k], (uint32_t)R[b][k], (uint32_t)l);
+                        }
                     }
                 }
             });
-            static_for<T0, T1>([&](auto tc) {
+            static_for<0, NTT>([&](auto tc) {
                 constexpr int t = tc;
-                if constexpr (g3_tile_pos<D>(SLOT, t) == k) {
-                    acc_ab[t - T0] = mfma_i8(A[tri_I(t)], B[tri_J(t)], acc_ab[t - T0]);
+                if constexpr (g3_has<D>(SLOT, t) && g3_tile_pos<D>(SLOT, t) == k) {
+                    constexpr int q = g3_rank<D>(SLOT, t);
+                    acc_ab[q] = mfma_i8(A[tri_I(t)], B[tri_J(t)], acc_ab[q]);
                     if constexpr (!g3_diag(t))
-                        acc_ba[t - T0] = mfma_i8(B[tri_I(t)], A[tri_J(t)], acc_ba[t - T0]);
-                    acc_rr[t - T0] = mfma_i8(R[tri_I(t)], R[tri_J(t)], acc_rr[t - T0]);
+                        acc_ba[q] = mfma_i8(B[tri_I(t)], A[tri_J(t)], acc_ba[q]);
+                    acc_rr[q] = mfma_i8(R[tri_I(t)], R[tri_J(t)], acc_rr[q]);
                 }
             });
         });
@@ -589,6 +598,7 @@ __device__ __forceinline__ void g3_dispatch(uint8_t *smem, const G3Args &a, cons
             g3_wave<D, W, ACC, MB>(smem, a, bt, a.volts); \
         break;
         XC_CASE(0) XC_CASE(1) XC_CASE(2) XC_CASE(3) XC_CASE(4) XC_CASE(5) XC_CASE(6) XC_CASE(7)
+        XC_CASE(8) XC_CASE(9) XC_CASE(10) XC_CASE(11) XC_CASE(12) XC_CASE(13) XC_CASE(14) XC_CASE(15)
 #undef XC_CASE
     default: break;
     }
