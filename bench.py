@@ -40,11 +40,11 @@ def kernel_source_sha() -> str:
     return sha()
 
 
-def measured_traffic(per_launch_algo_bytes: float):
+def measured_traffic(kernel: str):
     """HBM bytes per launch of the dominant kernel from the committed
     rocprofv3 FETCH_SIZE / WRITE_SIZE summary, if it was taken on the current
     kernel source; else None."""
-    p = os.path.join(PROFILES, "xc_mfma4f_tianlai_traffic.json")
+    p = os.path.join(PROFILES, f"{kernel}_tianlai_traffic.json")
     if not os.path.exists(p):
         return None
     try:
@@ -56,29 +56,51 @@ def measured_traffic(per_launch_algo_bytes: float):
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(volts_dev, n_chan_sample: int):
-    """The oracle as it stands, on a channel subset, one thread per channel
-    slice on the host cores."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(volts_dev, n_chan_sample: int, n_chan_single: int):
+    """The oracle as it stands on the host cores: one thread per channel
+    slice over n_chan_sample channels, and one thread over n_chan_single."""
     import concurrent.futures as cf
 
     import numpy as np
 
     import oracle
 
-    cores = min(16, len(os.sched_getaffinity(0)))
-    sub = volts_dev[:, :n_chan_sample, :].contiguous().cpu().numpy()
-    T, F, N = sub.shape
+    affinity = len(os.sched_getaffinity(0))
+    cores = min(16, affinity)
     lib = oracle.load_library()
-    chans = np.arange(F)
-    slices = [chans[k::cores] for k in range(cores)]
-    t0 = time.perf_counter()
-    with cf.ThreadPoolExecutor(cores) as ex:
-        list(ex.map(lambda c: oracle.xcorr(sub, 4, T, F, N, chans=c, lib=lib), slices))
-    dt = time.perf_counter() - t0
-    cmacs = F * (N * (N + 1) // 2) * T
-    return {"value": cmacs / dt, "unit": "CMAC/s", "cores": cores, "kind": "oracle",
-            "sample": f"{N} inputs x {F} of {N_CHANS} channels x {T} samples "
-                      f"({cmacs:.3e} CMAC) in {dt:.2f} s wall"}
+
+    def run(n_chan, threads):
+        sub = volts_dev[:, :n_chan, :].contiguous().cpu().numpy()
+        T, F, N = sub.shape
+        chans = np.arange(F)
+        slices = [chans[k::threads] for k in range(threads)]
+        t0 = time.perf_counter()
+        with cf.ThreadPoolExecutor(threads) as ex:
+            list(ex.map(lambda c: oracle.xcorr(sub, 4, T, F, N, chans=c, lib=lib), slices))
+        dt = time.perf_counter() - t0
+        cmacs = F * (N * (N + 1) // 2) * T
+        return cmacs / dt, f"{N} inputs x {F} of {N_CHANS} channels x {T} samples ({cmacs:.3e} CMAC) in {dt:.2f} s wall"
+
+    v_all, s_all = run(n_chan_sample, cores)
+    v_one, s_one = run(n_chan_single, 1)
+    return {"value": v_all, "unit": "CMAC/s", "cores": cores, "kind": "oracle", "sample": s_all,
+            "single_thread": {"value": v_one, "unit": "CMAC/s", "cores": 1, "sample": s_one},
+            "host": {"cpu_model": _cpu_model(), "os_cpu_count": os.cpu_count(), "affinity_cpus": affinity}}
+
+
+def _progress(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def _timed(fn, stream, reps: int, warmup: int = 2, after=None):
@@ -103,34 +125,64 @@ def _timed(fn, stream, reps: int, warmup: int = 2, after=None):
     return float(ms.mean()), ms
 
 
+def fp_error_metrics(approx, exact, N: int) -> dict:
+    """Error of an FP visibility set against the exact one, three ways:
+    max |dV| / sqrt(V_ii V_jj) (correlation-coefficient units), max |dV| / |V|
+    over entries with |V| >= 1e-3 sqrt(V_ii V_jj), and max |dV|."""
+    import torch
+    idx = torch.arange(N, device=exact.device)
+    diag = idx * (idx + 1) // 2 + idx
+    ii = torch.repeat_interleave(idx, idx + 1)
+    jj = torch.cat([torch.arange(i + 1, device=exact.device) for i in range(N)])
+    auto = exact[..., diag, 0]                            # [F][N], real and >= 0
+    norm = torch.sqrt(auto[:, ii] * auto[:, jj]).clamp_min(1e-300)
+    d = torch.linalg.vector_norm(approx - exact, dim=-1)
+    mag = torch.linalg.vector_norm(exact, dim=-1)
+    big = mag >= 1e-3 * norm
+    return {"max_err_over_sqrt_autos": float((d / norm).max()),
+            "max_rel_err_large_entries": float((d[big] / mag[big]).max()) if bool(big.any()) else 0.0,
+            "max_abs_err": float(d.max()), "max_abs_value": float(mag.max())}
+
+
 def bench_precision8(dev, stream, reps: int) -> dict:
-    """192 inputs x 512 channels x 8192 samples of 8+8-bit noise: int8 and FP16
-    paths; the FP16 error is stated against the int8 path's exact result."""
+    """8+8-bit input through the exact int8 path and the FP16-MFMA/FP32 path:
+    192 inputs x 512 channels x 8192 samples (sigma 20), and a stress case of
+    192 inputs x 16 channels x 65,536 samples (sigma 60) whose sums pass 2^24.
+    FP16 errors are stated against the int8 path's exact result (bit-exact to
+    the FP64 oracle on these inputs, which the parity tests check)."""
     import torch
 
     from paper_2406_19013_amd import synth
     from paper_2406_19013_amd import xcorr as X
 
-    N, F, T = 192, 512, 8192
-    with torch.cuda.stream(stream):
-        v = synth.precision8(device=dev)
-    stream.synchronize()
-    ops = OPS_PER_CMAC * N * (N + 1) // 2 * F * T
-    res, outs = {"workload": "precision-192in-512ch-8192t-8bit"}, {}
-    for name, path, peak in (("int8_mfma", X.PATH_I8_MFMA, INT8_PEAK_TOPS), ("f16_mfma", X.PATH_F16_MFMA, 2500.0)):
-        c = X.Correlator(N, F, 8, path, device=dev)
-        outs[name] = torch.empty((F, N * (N + 1) // 2, 2), dtype=torch.float32 if path == X.PATH_F16_MFMA
-                                 else torch.int32, device=dev)
-        ms, _ = _timed(lambda: c.ingest(v, T, stream=stream), stream, reps,
-                       after=lambda: c.dump(outs[name], stream=stream))
+    res = {}
+    for label, (F, T, sigma), timed in (("precision-192in-512ch-8192t-8bit", (512, 8192, 20.0), True),
+                                        ("stress-192in-16ch-65536t-8bit-sigma60", (16, 65536, 60.0), False)):
+        N = 192
+        with torch.cuda.stream(stream):
+            v = synth.gaussian_volts(N, F, T, sigma=sigma, bits=8, seed=(synth.BASE_SEED, 3, int(sigma)),
+                                     device=dev) if not timed else synth.precision8(device=dev)
         stream.synchronize()
-        res[name] = {"ingest_ms": ms, "tops": ops / ms / 1e9, "peak": peak, "frac": ops / ms / 1e9 / peak,
-                     "tile": c.stats()["tile"]}
-        c.close()
-    exact = outs["int8_mfma"].double()
-    d = (outs["f16_mfma"].double() - exact)
-    res["f16_max_abs_err_vs_exact"] = float(d.abs().max())
-    res["max_abs_value"] = float(exact.abs().max())
+        ops = OPS_PER_CMAC * N * (N + 1) // 2 * F * T
+        r, outs = {"workload": label}, {}
+        for name, path, peak in (("int8_mfma", X.PATH_I8_MFMA, INT8_PEAK_TOPS), ("f16_mfma", X.PATH_F16_MFMA, 2500.0)):
+            c = X.Correlator(N, F, 8, path, device=dev)
+            outs[name] = torch.empty((F, N * (N + 1) // 2, 2), dtype=torch.float32 if path == X.PATH_F16_MFMA
+                                     else torch.int32, device=dev)
+            if timed:
+                ms, _ = _timed(lambda: c.ingest(v, T, stream=stream), stream, reps,
+                               after=lambda: c.dump(outs[name], stream=stream))
+                r[name] = {"ingest_ms": ms, "tops": ops / ms / 1e9, "peak": peak, "frac": ops / ms / 1e9 / peak,
+                           "tile": c.stats()["tile"]}
+            else:
+                c.ingest(v, T, stream=stream)
+                c.dump(outs[name], stream=stream)
+            stream.synchronize()
+            c.close()
+        exact = outs["int8_mfma"].double()
+        r["f16_vs_exact"] = fp_error_metrics(outs["f16_mfma"].double(), exact, N)
+        res["config3" if timed else "stress"] = r
+        del v, outs, exact
     return res
 
 
@@ -146,6 +198,12 @@ def bench_batched(dev, stream, reps: int) -> dict:
         vs = synth.batched(device=dev)
     stream.synchronize()
     T = vs[0].shape[0]
+    # tiles tuned on the batched kernel into a private tune cache
+    import tempfile
+    cache_dir = tempfile.mkdtemp(prefix="xcorr_tune_")
+    prev_cache = os.environ.get("XCORR_TUNE_CACHE")
+    os.environ["XCORR_TUNE_CACHE"] = os.path.join(cache_dir, "tune.txt")
+    tuned = [X.autotune(N, F, device=dev, stream=stream, batch=True) for N, F in synth.BATCH_ARRAYS]
     cors = [X.Correlator(N, F, 4, X.PATH_I8_MFMA, device=dev) for N, F in synth.BATCH_ARRAYS]
     cmac = sum(N * (N + 1) // 2 * F * T for N, F in synth.BATCH_ARRAYS)
     b = X.Batch(cors, device=dev)
@@ -163,8 +221,25 @@ def bench_batched(dev, stream, reps: int) -> dict:
 
     single_ms, _ = _timed(singles, stream, reps, after=dumps)
     stream.synchronize()
+    # the batched launch captured once in a graph and replayed
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(g, stream=stream):
+            b.ingest(vs, stream=stream)
+    stream.synchronize()
+    def replay():
+        with torch.cuda.stream(stream):
+            g.replay()
+
+    graph_ms, _ = _timed(replay, stream, reps, after=dumps)
+    stream.synchronize()
+    if prev_cache is None:
+        os.environ.pop("XCORR_TUNE_CACHE", None)
+    else:
+        os.environ["XCORR_TUNE_CACHE"] = prev_cache
     res = {"workload": "batched-4arrays-2048t-4bit", "arrays": [list(a) for a in synth.BATCH_ARRAYS],
-           "tiles": b.tiles, "batch_ms": batch_ms, "separate_launches_ms": single_ms,
+           "tiles": b.tiles, "tuned_tiles": tuned, "batch_ms": batch_ms, "graph_replay_ms": graph_ms,
+           "separate_launches_ms": single_ms,
            "cmac_per_s": cmac / (batch_ms / 1e3), "frac_of_int8_peak": OPS_PER_CMAC * cmac / (batch_ms / 1e3) / 1e12
            / INT8_PEAK_TOPS}
     b.close()
@@ -210,7 +285,8 @@ def bench_streaming(dev, n_blocks: int, paced_blocks: int, concurrent_blocks: in
     wall = time.perf_counter() - t0
     st = p.stats()
     res["n192_device_unpaced"] = {"blocks": n_blocks, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
-                                  "max_ms": st["max_ms"], "rtf": n_blocks * span_s / wall, "dumps": st["dumps"]}
+                                  "max_ms": st["max_ms"], "rtf": n_blocks * span_s / wall, "dumps": st["dumps"],
+                                  "submit_p50_ms": st["submit_p50_ms"], "submit_p99_ms": st["submit_p99_ms"]}
     # the same stream with 8 blocks per launch (the accumulators are read and
     # written once per 8 blocks)
     p.set_fuse(8)
@@ -223,7 +299,8 @@ def bench_streaming(dev, n_blocks: int, paced_blocks: int, concurrent_blocks: in
     wall = time.perf_counter() - t0
     st = p.stats()
     res["n192_device_unpaced_fuse8"] = {"blocks": n_blocks, "group_p50_ms": st["p50_ms"],
-                                        "group_p99_ms": st["p99_ms"], "rtf": n_blocks * span_s / wall}
+                                        "group_p99_ms": st["p99_ms"], "rtf": n_blocks * span_s / wall,
+                                        "submit_p50_ms": st["submit_p50_ms"], "submit_p99_ms": st["submit_p99_ms"]}
     p.close()
 
     # the same stream arriving out of order (each block up to 8 places late)
@@ -283,7 +360,9 @@ def bench_streaming(dev, n_blocks: int, paced_blocks: int, concurrent_blocks: in
     p.drain()
     st = p.stats()
     res["n192_host_h2d_paced"] = {"blocks": paced_blocks, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
-                                  "max_ms": st["max_ms"]}
+                                  "max_ms": st["max_ms"], "submit_p50_ms": st["submit_p50_ms"],
+                                  "submit_p99_ms": st["submit_p99_ms"], "submit_max_ms": st["submit_max_ms"],
+                                  "clock_anchor_err_ms": st["clock_anchor_err_ms"]}
     # unpaced H2D: the rate the host link sustains
     p.reset_latency()
     t0 = time.perf_counter()
@@ -325,6 +404,21 @@ def bench_streaming(dev, n_blocks: int, paced_blocks: int, concurrent_blocks: in
     res["concurrent"] = {"arrays": list(arrays), "admitted": admitted, "admitted_bytes": used,
                          "blocks_per_array": concurrent_blocks, "rtf": concurrent_blocks * span_s / wall,
                          "p99_ms": {str(n): ps[n].stats()["p99_ms"] for n in live}}
+    # the same three arrays with 8 blocks per launch
+    for n in live:
+        ps[n].set_fuse(8)
+        ps[n].drain()
+        ps[n].reset_latency()
+    t0 = time.perf_counter()
+    for k in range(concurrent_blocks):
+        for n in live:
+            ps[n].push(pools[n][k % pool_n], out=outs[n])
+    for n in live:
+        ps[n].drain()
+    wall = time.perf_counter() - t0
+    res["concurrent_fuse8"] = {"blocks_per_array": concurrent_blocks, "rtf": concurrent_blocks * span_s / wall,
+                               "group_p99_ms": {str(n): ps[n].stats()["p99_ms"] for n in live},
+                               "submit_p99_ms": {str(n): ps[n].stats()["submit_p99_ms"] for n in live}}
     for n in live:
         ps[n].close()
         cs[n].close()
@@ -338,13 +432,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--cpu-channels", type=int, default=256)
+    ap.add_argument("--cpu-channels-single", type=int, default=24)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-path comparison")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the precision, batched and streaming workloads")
     ap.add_argument("--stream-blocks", type=int, default=2048)
-    ap.add_argument("--paced-blocks", type=int, default=64)
+    ap.add_argument("--paced-blocks", type=int, default=512)
     ap.add_argument("--concurrent-blocks", type=int, default=128)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -408,7 +503,7 @@ def main():
     evs, wall = timed(fused_step, mf, 2)
     step_ms = np.array([e[0].elapsed_time(e[1]) for e in evs])
     ms_per_step = wall * 1e3 / args.steps
-    kernel_ms = step_ms   # the step is one xc_mfma4f_kernel launch
+    kernel_ms = step_ms   # the step is one correlation kernel launch
     # the same work as separate ingest and dump calls
     evs2, wall2 = timed(step, mf, 3)
     ingest_ms = np.array([e[0].elapsed_time(e[1]) for e in evs2])
@@ -432,8 +527,25 @@ def main():
     achieved_tops = algo_ops / ingest_s / 1e12
     in_bytes = T * F * N
     acc_bytes = F * P * 8
-    traffic = measured_traffic(in_bytes + acc_bytes)
+    kernel = X.xcorr_autotune_kernel(mf.cfg)
+    traffic = measured_traffic(kernel)
     dump_gbs = 2 * acc_bytes / (float(dump_ms.mean()) / 1e3) / 1e9
+
+    # measured ceilings of this GPU: int8 MFMA issue on voltage bytes, and
+    # the input streamed into LDS the way the correlation kernel reads it
+    cus = torch.cuda.get_device_properties(dev).multi_processor_count
+    chk = torch.empty(512 * cus, dtype=torch.int32, device=dev)
+    ceil = {}
+    for name, kind, iters in (("mfma_int8", X.CEILING_MFMA_I8, 2000), ("stream_read", X.CEILING_STREAM, 1)):
+        box = {}
+
+        def launch():
+            box["ops"] = X.xcorr_ceiling(kind, volts, T, F, N, iters, chk, stream=stream)
+
+        ms, _ = _timed(launch, stream, max(10, args.steps // 2))
+        ceil[name] = box["ops"] / (ms / 1e3)
+    mfma_ceiling_tops = ceil["mfma_int8"] / 1e12
+    stream_ceiling_gbs = ceil["stream_read"] / 1e9
 
     result = {
         "metric": "complex MAC/s (int8 MFMA path), real-time factor vs plain path, p99 step latency",
@@ -461,22 +573,35 @@ def main():
         "dump_hbm_gbs": dump_gbs,
         "roofline": {"bound": "mfma", "achieved": achieved_tops, "peak": INT8_PEAK_TOPS,
                      "unit": "TFLOP/s", "frac": achieved_tops / INT8_PEAK_TOPS, "traffic": traffic,
-                     "kernel": "xc_mfma4f_kernel", "algorithmic_ops_per_launch": algo_ops,
+                     "ops": "int8 (2 per multiply-add, 8 per complex MAC), 10^12 per s",
+                     "kernel": kernel, "algorithmic_ops_per_launch": algo_ops,
+                     "measured_peak": mfma_ceiling_tops, "frac_of_measured_peak": achieved_tops / mfma_ceiling_tops,
                      "hbm_algorithmic_bytes_per_launch": in_bytes + acc_bytes,
-                     "hbm_frac": (in_bytes + acc_bytes) / ingest_s / 1e9 / HBM_PEAK_GBS},
+                     "hbm_gbs": (in_bytes + acc_bytes) / ingest_s / 1e9,
+                     "hbm_frac": (in_bytes + acc_bytes) / ingest_s / 1e9 / HBM_PEAK_GBS,
+                     "hbm_frac_of_measured_stream": (in_bytes + acc_bytes) / ingest_s / 1e9 / stream_ceiling_gbs},
+        "ceilings": {"mfma_int8_tops": mfma_ceiling_tops, "mfma_int8_frac_of_nominal": mfma_ceiling_tops / INT8_PEAK_TOPS,
+                     "stream_read_gbs": stream_ceiling_gbs, "stream_read_frac_of_nominal": stream_ceiling_gbs / HBM_PEAK_GBS,
+                     "note": "MFMA: 8 waves per CU issuing independent 32x32x32 int8 MFMAs on voltage bytes; "
+                             "stream: the input read into LDS with the correlation kernel's grid and loads"},
+        "stages": {"ingest_read_gbs": in_bytes / ingest_s / 1e9, "dump_gbs": dump_gbs},
     }
     mf.close()
+    _progress("headline workload done")
     if not args.no_extra:
         del volts
         result["precision8"] = bench_precision8(dev, stream, max(5, args.steps // 2))
+        _progress("precision workload done")
         result["batched"] = bench_batched(dev, stream, max(5, args.steps // 2))
+        _progress("batched workload done")
         result["streaming"] = bench_streaming(dev, args.stream_blocks, args.paced_blocks, args.concurrent_blocks)
+        _progress("streaming workload done")
         result["latency_ms"]["p99_block_stream"] = result["streaming"]["n192_device_unpaced"]["p99_ms"]
     if not args.no_cpu:
         with torch.cuda.stream(stream):
             volts = synth.tianlai(device=dev)
         stream.synchronize()
-        result["cpu_baseline"] = cpu_baseline(volts, args.cpu_channels)
+        result["cpu_baseline"] = cpu_baseline(volts, args.cpu_channels, args.cpu_channels_single)
     print(json.dumps(result), flush=True)
 
 

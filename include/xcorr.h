@@ -394,6 +394,29 @@ int xcorr_reorder_destroy(xcorr_reorder *r);
 int xcorr_correlate_static(const xcorr_config *cfg, const void *d_volts, int64_t n_samples, void *d_out,
                            int64_t *n_integrated, void *stream);
 
+/*
+ * Hardware ceilings for the roofline of a benchmark (no correlation is
+ * computed).  Enqueued on `stream`; the caller times them with events.
+ *   XCORR_CEILING_MFMA_I8: one work-group of 8 waves per compute unit (two
+ *     per SIMD, as the correlation kernel) issues `iters` rounds of 16
+ *     independent 32x32x32 int8 MFMAs per wave on operands read from d_volts
+ *     (voltage bytes, at least 4096 of them, so the multipliers toggle as on
+ *     real data); *ops = int8 ops done (2 per multiply-add).
+ *   XCORR_CEILING_STREAM: the [n_samples][n_chans][n_inputs] packed input of
+ *     a 4+4-bit launch is streamed into LDS with the correlation kernel's
+ *     grid, channel mapping, 64-sample chunks, 16-byte LDS-DMA loads and
+ *     cache policy, and nothing else is done with it; *ops = bytes read.
+ * d_out receives one int32 checksum per thread: out_ints must be at least
+ * 512 x (compute units).  Errors: XCORR_E_INVAL for an unknown kind, NULL or
+ * unaligned (16 B) pointers, n_inputs outside 16..256 or not a multiple of
+ * 16, 64 * n_chans * n_inputs >= 2^31 - 16, iters < 1 (MFMA) or a short
+ * d_out; XCORR_E_HIP if the launch fails.
+ */
+#define XCORR_CEILING_MFMA_I8 0
+#define XCORR_CEILING_STREAM 1
+int xcorr_ceiling(int32_t kind, const void *d_volts, int64_t n_samples, int32_t n_chans, int32_t n_inputs,
+                  int64_t iters, void *d_out, int64_t out_ints, double *ops, void *stream);
+
 const char *xcorr_strerror(int code);
 /* Detail of the last XCORR_E_HIP / XCORR_E_DEVICE on this thread. */
 const char *xcorr_last_error(void);

@@ -7,10 +7,9 @@ namespace xc {
 namespace {
 
 // One work-group per (channel, region), regions as in the per-role kernel.
-// Two work-groups per CU for D <= 3 (128 registers per wave; at D = 3 the
-// compiler spills 32 bytes per lane, still faster than one work-group with
-// 256 registers), one above.
-constexpr int fused_wgs_per_cu(int D) { return D <= 3 ? 2 : 1; }
+// Two work-groups per CU for D <= 2 (128 registers per wave), one above: at
+// D = 3 the 128-register budget spills.
+constexpr int fused_wgs_per_cu(int D) { return D <= 2 ? 2 : 1; }
 
 template <int D, int VEC, int ACC>
 __global__ __launch_bounds__(kMfmaThreads)

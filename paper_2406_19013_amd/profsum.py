@@ -29,11 +29,11 @@ import statistics
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ("xcorr_mfma4f.hip", "xc_mfma4.h", "xc_mfma.h", "xc_device.h", "xcorr_internal.h")
+KERNEL_SOURCES = ("xcorr_gauss4.hip", "xc_gauss4.h", "xc_mfma4.h", "xc_mfma.h", "xc_device.h", "xcorr_internal.h")
 
 
 def kernel_source_sha() -> str:
-    """sha256[:16] over the sources of the default 4+4-bit MFMA kernel."""
+    """sha256[:16] over the sources of the default 4+4-bit MFMA kernel (three-product)."""
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
         with open(os.path.join(HERE, "csrc", name), "rb") as fh:

@@ -152,6 +152,8 @@ def load(path: str | None = None):
             "xcorr_plan_tile": [cfgp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                 ctypes.POINTER(ctypes.c_int32)],
             "xcorr_correlate_static": [cfgp, vp, i64, vp, ctypes.POINTER(i64), vp],
+            "xcorr_ceiling": [ctypes.c_int32, vp, i64, ctypes.c_int32, ctypes.c_int32, i64, vp, i64,
+                              ctypes.POINTER(ctypes.c_double), vp],
             "xcorr_pipe_query": [vp, ctypes.c_int, i64, ctypes.POINTER(sz)],
             "xcorr_pipe_init": [vp, ctypes.c_int, i64, i64, vp, sz, vp, vp, ctypes.POINTER(vp)],
             "xcorr_pipe_push": [vp, vp, ctypes.c_int, u64, vp, ctypes.POINTER(ctypes.c_int)],
@@ -468,6 +470,20 @@ def xcorr_correlate_static(cfg: Config, volts, n_samples: int, out, stream=None)
                                          ctypes.c_void_p(out.data_ptr()), ctypes.byref(n), _stream_handle(stream)),
            "xcorr_correlate_static")
     return n.value
+
+
+CEILING_MFMA_I8, CEILING_STREAM = 0, 1
+
+
+def xcorr_ceiling(kind: int, volts, n_samples: int, n_chans: int, n_inputs: int, iters: int, out,
+                  stream=None) -> float:
+    """Enqueue a hardware-ceiling kernel; returns the ops (MFMA) or bytes
+    (stream) it performs."""
+    ops = ctypes.c_double()
+    _check(load().xcorr_ceiling(int(kind), ctypes.c_void_p(volts.data_ptr()), int(n_samples), int(n_chans),
+                                int(n_inputs), int(iters), ctypes.c_void_p(out.data_ptr()), int(out.numel()),
+                                ctypes.byref(ops), _stream_handle(stream)), "xcorr_ceiling")
+    return ops.value
 
 
 def xcorr_strerror(code: int) -> str:
