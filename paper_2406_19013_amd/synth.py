@@ -206,3 +206,66 @@ def stream_block(N: int, F: int, block: int, *, array_id: int, T: int = 1024,
     return gaussian_volts(N, F, T, sigma=2.5, bits=4, seed=(BASE_SEED, 5, array_id),
                           tone=Tone(amp=2.5, delta=0.01, drift=1e-5), block=block,
                           t0=block * T, device=device)
+
+
+# ---- raw ADC samples for the F-engine front end -------------------------------
+# Paper Section 2.2 "F-engine": 8-bit samples at 250 Msps (Fix_8_7 words, here
+# their integer codes -128 .. 127), one real time series per input.
+
+@dataclass(frozen=True)
+class AdcTone:
+    freq: float        # cycles per ADC sample
+    amp: float         # amplitude in ADC codes
+
+
+def adc_samples(N: int, S: int, *, sigma: float, seed: tuple, tones=(), device="cpu",
+                chunk: int = 1 << 20) -> torch.Tensor:
+    """ADC codes ``[N][S]`` int8: Gaussian noise (sigma in codes) plus real
+    tones ``amp * cos(2 pi freq s + phase)`` with a seeded phase per (tone,
+    input); rounded half to even, clipped to [-128, 127]."""
+    g = _gen(seed_of(*seed), device)
+    phases = []
+    if tones:
+        gp = _gen(seed_of(*seed, _PHASE_TAG), device)
+        phases = [torch.rand(N, generator=gp, device=device, dtype=torch.float64) * 2 * math.pi for _ in tones]
+    out = torch.empty((N, S), dtype=torch.int8, device=device)
+    for s0 in range(0, S, chunk):
+        sc = min(chunk, S - s0)
+        x = torch.randn((N, sc), generator=g, device=device, dtype=torch.float32) * sigma
+        if tones:
+            s = torch.arange(s0, s0 + sc, device=device, dtype=torch.float64)
+            for tone, ph in zip(tones, phases):
+                # the phase 2 pi f s reduced modulo 2 pi in float64 before the cosine
+                arg = torch.remainder(tone.freq * s, 1.0) * (2 * math.pi)
+                x += (tone.amp * torch.cos(arg[None, :] + ph[:, None])).to(torch.float32)
+        out[:, s0:s0 + sc] = quantise(x, -128, 127).to(torch.int8)
+    return out
+
+
+def eq_gains(N: int, F: int, *, base: float, seed: tuple, spread: float = 1.25, device="cpu") -> torch.Tensor:
+    """EQ gains ``[N][F]`` float32: base times a log-uniform factor in
+    [1 / spread, spread] per (input, channel)."""
+    g = _gen(seed_of(*seed), device)
+    u = torch.rand((N, F), generator=g, device=device, dtype=torch.float64) * 2 - 1
+    return (base * torch.exp(u * math.log(spread))).to(torch.float32)
+
+
+# Per-input ADC noise of the F-engine workloads and the EQ gain that brings a
+# channel's components to about 2.5 codes of the 4-bit output (per component
+# sigma of a channel = sigma_adc * sqrt(sum h^2 / 2) for the 4 x 2048
+# Hamming-sinc prototype, sum h^2 = 1649.6).
+FE_ADC_SIGMA = 16.0
+FE_EQ_BASE = 0.00544
+
+
+def fengine_adc(device="cpu", N: int = 192, T: int = 4096, P: int = 2048, taps: int = 4) -> torch.Tensor:
+    """ADC codes for T spectra of N inputs: noise (sigma 16 codes) plus two
+    tones, one on a channel centre and one between channels."""
+    S = (T + taps - 1) * P
+    return adc_samples(N, S, sigma=FE_ADC_SIGMA, seed=(BASE_SEED, 6),
+                       tones=(AdcTone(freq=300.0 / P, amp=12.0), AdcTone(freq=700.5 / P, amp=8.0)),
+                       device=device)
+
+
+def fengine_gains(device="cpu", N: int = 192, F: int = 1024) -> torch.Tensor:
+    return eq_gains(N, F, base=FE_EQ_BASE, seed=(BASE_SEED, 6, 1), device=device)
