@@ -248,6 +248,46 @@ def bench_batched(dev, stream, reps: int) -> dict:
     return res
 
 
+def bench_fengine(dev, stream, reps: int) -> dict:
+    """F-engine front end on 192 inputs x 4096 spectra (8-bit ADC codes at
+    250 Msps: 33.55 ms of sky, 1.61 GB in, 805 MB of 4+4-bit codes out), then
+    the end-to-end step ADC -> codes -> one X-engine integration."""
+    import torch
+
+    from paper_2406_19013_amd import synth
+    from paper_2406_19013_amd import xcorr as X
+
+    N, M, P, F = 192, 4096, X.FE_POINTS, X.FE_CHANS
+    with torch.cuda.stream(stream):
+        adc = synth.fengine_adc(device=dev, N=N, T=M)
+        gains = synth.fengine_gains(device=dev, N=N, F=F)
+    h = torch.from_numpy(X.xcorr_pfb_prototype()).to(dev)
+    codes = torch.empty((M, F, N), dtype=torch.uint8, device=dev)
+    stream.synchronize()
+    fe_ms, _ = _timed(lambda: X.xcorr_fengine(adc, h, gains, codes, M, stream=stream), stream, reps)
+    c = X.Correlator(N, F, 4, X.PATH_I8_MFMA, device=dev)
+    vis = torch.empty((F, N * (N + 1) // 2, 2), dtype=torch.int32, device=dev)
+
+    def end_to_end():
+        X.xcorr_fengine(adc, h, gains, codes, M, stream=stream)
+        c.ingest_dump(codes, vis, stream=stream)
+
+    e2e_ms, _ = _timed(end_to_end, stream, reps)
+    stream.synchronize()
+    c.close()
+    span_s = M * P / 250e6
+    in_bytes, out_bytes = adc.numel(), codes.numel()
+    # float work per (input, spectrum): FIR 2 x 4 x 2048, complex FFT
+    # 5 x 1024 x log2(1024), real-spectrum unpack and EQ about 16 x 1024
+    flops = N * M * (8 * P + 5 * 1024 * 10 + 16 * 1024)
+    return {"workload": "fengine-192in-4096spectra-2048pt-4tap", "ms": fe_ms,
+            "hbm_gbs": (in_bytes + out_bytes) / (fe_ms / 1e3) / 1e9,
+            "hbm_frac": (in_bytes + out_bytes) / (fe_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+            "gflops": flops / (fe_ms / 1e3) / 1e9, "fp32_vector_frac": flops / (fe_ms / 1e3) / 157.3e12,
+            "rtf": span_s / (fe_ms / 1e3), "data_span_ms": span_s * 1e3,
+            "end_to_end_ms": e2e_ms, "end_to_end_rtf": span_s / (e2e_ms / 1e3)}
+
+
 def bench_streaming(dev, n_blocks: int, paced_blocks: int, concurrent_blocks: int) -> dict:
     """1024-sample blocks of 4096 channels (33.55 ms of data each), a dump
     every 128 blocks: the 192-input stream device-resident (unpaced) and from
@@ -596,6 +636,8 @@ def main():
         _progress("batched workload done")
         result["streaming"] = bench_streaming(dev, args.stream_blocks, args.paced_blocks, args.concurrent_blocks)
         _progress("streaming workload done")
+        result["fengine"] = bench_fengine(dev, stream, max(5, args.steps // 2))
+        _progress("F-engine workload done")
         result["latency_ms"]["p99_block_stream"] = result["streaming"]["n192_device_unpaced"]["p99_ms"]
     if not args.no_cpu:
         with torch.cuda.stream(stream):

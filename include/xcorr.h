@@ -395,6 +395,43 @@ int xcorr_correlate_static(const xcorr_config *cfg, const void *d_volts, int64_t
                            int64_t *n_integrated, void *stream);
 
 /*
+ * F-engine front end (paper Section 2.2, "F-engine"): raw ADC samples ->
+ * polyphase filter bank -> 1024 channels -> EQ -> 4+4-bit codes in the
+ * X-engine's input order.  Fixed shape: 2048-point filter bank (real FFT,
+ * the first 1024 bins kept), 4 taps.
+ *
+ * xcorr_pfb_prototype (host only): the library's prototype filter,
+ * h[n] = w[n] sinc(n / n_points - taps / 2), n < taps * n_points, w the
+ * symmetric Hamming window 0.54 - 0.46 cos(2 pi n / (taps n_points - 1)),
+ * written as float32 to h_out (caller-owned, taps * n_points entries).
+ * Errors: XCORR_E_INVAL for n_points < 2, taps < 1 or a NULL pointer.
+ *
+ * xcorr_fengine (async on `stream`): d_adc holds int8 ADC codes [N][S] (input
+ * i's samples at i * S, S = n_samples); spectrum m (m < n_spectra) filters
+ * samples [2048 m, 2048 (m + 4)) as y[q] = sum_k h[2048 k + q] x[2048 (m + k) + q]
+ * with d_coeffs the 8192 prototype coefficients (float32), takes the real
+ * FFT of y, multiplies channel c of input i by d_gains[i * 1024 + c]
+ * (float32 EQ gain), rounds each part half to even and clips to [-8, 7], and
+ * writes the packed byte (real part in the high nibble) to
+ * d_out[(m * 1024 + c) * N + i]: uint8 [n_spectra][1024][N], the layout
+ * xcorr_ingest reads.  Arithmetic in float32.  Requirements (else
+ * XCORR_E_INVAL, nothing enqueued): N a positive multiple of 16; S a
+ * multiple of 16 and at least 8192; 1 <= n_spectra <= S / 2048 - 3; d_adc,
+ * d_coeffs, d_gains and d_out 16-byte aligned.  XCORR_E_HIP if the launch
+ * fails.  All buffers are caller-owned and must stay valid until the stream
+ * passes this call.
+ *
+ * xcorr_pfb_spectra: the same filter bank without EQ and requantisation;
+ * writes the complex spectra as float32 (re, im) pairs to
+ * d_out[((i * n_spectra + m) * 1024 + c) * 2 + {0, 1}].  Same requirements.
+ */
+int xcorr_pfb_prototype(int32_t n_points, int32_t taps, float *h_out);
+int xcorr_fengine(const void *d_adc, int64_t n_samples, int32_t n_inputs, const float *d_coeffs,
+                  const float *d_gains, int64_t n_spectra, void *d_out, void *stream);
+int xcorr_pfb_spectra(const void *d_adc, int64_t n_samples, int32_t n_inputs, const float *d_coeffs,
+                      int64_t n_spectra, void *d_out, void *stream);
+
+/*
  * Hardware ceilings for the roofline of a benchmark (no correlation is
  * computed).  Enqueued on `stream`; the caller times them with events.
  *   XCORR_CEILING_MFMA_I8: one work-group of 8 waves per compute unit (two

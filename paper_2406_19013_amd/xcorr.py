@@ -152,6 +152,9 @@ def load(path: str | None = None):
             "xcorr_plan_tile": [cfgp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                 ctypes.POINTER(ctypes.c_int32)],
             "xcorr_correlate_static": [cfgp, vp, i64, vp, ctypes.POINTER(i64), vp],
+            "xcorr_pfb_prototype": [ctypes.c_int32, ctypes.c_int32, vp],
+            "xcorr_fengine": [vp, i64, ctypes.c_int32, vp, vp, i64, vp, vp],
+            "xcorr_pfb_spectra": [vp, i64, ctypes.c_int32, vp, i64, vp, vp],
             "xcorr_ceiling": [ctypes.c_int32, vp, i64, ctypes.c_int32, ctypes.c_int32, i64, vp, i64,
                               ctypes.POINTER(ctypes.c_double), vp],
             "xcorr_pipe_query": [vp, ctypes.c_int, i64, ctypes.POINTER(sz)],
@@ -470,6 +473,40 @@ def xcorr_correlate_static(cfg: Config, volts, n_samples: int, out, stream=None)
                                          ctypes.c_void_p(out.data_ptr()), ctypes.byref(n), _stream_handle(stream)),
            "xcorr_correlate_static")
     return n.value
+
+
+FE_POINTS, FE_CHANS, FE_TAPS = 2048, 1024, 4
+
+
+def xcorr_pfb_prototype(n_points: int = FE_POINTS, taps: int = FE_TAPS):
+    """The library's prototype filter (float32 numpy array, host)."""
+    import numpy as np
+    h = np.empty(n_points * taps, dtype=np.float32)
+    _check(load().xcorr_pfb_prototype(int(n_points), int(taps), ctypes.c_void_p(h.ctypes.data)),
+           "xcorr_pfb_prototype")
+    return h
+
+
+def fe_n_spectra(n_samples: int) -> int:
+    return max(0, n_samples // FE_POINTS - FE_TAPS + 1)
+
+
+def xcorr_fengine(adc, coeffs, gains, out, n_spectra: int | None = None, stream=None):
+    """ADC codes adc [N][S] int8 -> packed 4+4-bit codes out [n_spectra][1024][N]."""
+    N, S = adc.shape
+    n_spectra = fe_n_spectra(S) if n_spectra is None else n_spectra
+    _check(load().xcorr_fengine(ctypes.c_void_p(adc.data_ptr()), int(S), int(N), ctypes.c_void_p(coeffs.data_ptr()),
+                                ctypes.c_void_p(gains.data_ptr()), int(n_spectra), ctypes.c_void_p(out.data_ptr()),
+                                _stream_handle(stream)), "xcorr_fengine")
+
+
+def xcorr_pfb_spectra(adc, coeffs, out, n_spectra: int | None = None, stream=None):
+    """ADC codes adc [N][S] int8 -> complex spectra out [N][n_spectra][1024][2] float32."""
+    N, S = adc.shape
+    n_spectra = fe_n_spectra(S) if n_spectra is None else n_spectra
+    _check(load().xcorr_pfb_spectra(ctypes.c_void_p(adc.data_ptr()), int(S), int(N),
+                                    ctypes.c_void_p(coeffs.data_ptr()), int(n_spectra),
+                                    ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)), "xcorr_pfb_spectra")
 
 
 CEILING_MFMA_I8, CEILING_STREAM = 0, 1
