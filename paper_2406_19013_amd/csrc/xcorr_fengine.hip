@@ -3,17 +3,23 @@
 // 1024 channels -> per-(input, channel) EQ gain -> 4+4-bit requantisation ->
 // corner turn into the X-engine's [T][F][N] order.
 //
-// One work-group = one spectrum m of 64 inputs; 8 waves, each filtering and
-// transforming 8 of the inputs one after the other.  Per input and spectrum:
+// Persistent work-groups of 4 waves; an item is one spectrum m of 16 inputs,
+// 4 per wave, each filtered and transformed by one wave.  Per input and
+// spectrum:
 //   y[q] = sum_k h[k P + q] x[(m + k) P + q]            q < P = 2048
 //   z[n] = y[2n] + i y[2n + 1]                          n < 1024
-//   Z    = 1024-point complex DFT of z (radix 16 x 16 x 4, two LDS exchanges)
+//   Z    = 1024-point complex DFT of z (radix 16 x 16 x 4)
 //   Y[c] = (Z[c] + Z*[N - c]) / 2 - i W^c (Z[c] - Z*[N - c]) / 2,  W = e^{-2 pi i / 2048}
 //   code = pack(clip(rint(g Re Y)), clip(rint(g Im Y)))  for channels c < 1024
-// The FIR coefficients a lane needs (4 taps x 16 sample pairs) stay in its
-// registers for all 8 inputs; the codes of the 64 inputs are gathered in LDS
-// and leave as one 64-byte row per (spectrum, channel).  Arithmetic in fp32;
-// rounding is round-half-to-even.
+// A lane reads 32 consecutive samples of each tap with 16-byte loads (one
+// input ahead of the one it transforms) and keeps the 128 prototype
+// coefficients of its sample positions in registers for the work-group's
+// life; four LDS exchanges per transform (into the stride-64 order, between
+// the three radix passes, and for the Z[N - c] pairs).  Twiddles are built
+// per lane from one base value by short power products (at most three
+// roundings deep).  The 16 inputs' codes are gathered in LDS and leave as one
+// 16-byte row per (spectrum, channel).  Arithmetic in fp32; rounding is
+// round-half-to-even.
 #include "xcorr.h"
 #include "xcorr_internal.h"
 
@@ -30,13 +36,14 @@ namespace {
 constexpr int kFeP = 2048;          // real points per spectrum
 constexpr int kFeN = kFeP / 2;      // complex FFT size and channel count
 constexpr int kFeTaps = 4;
-constexpr int kFeGroup = 64;        // inputs per work-group
-constexpr int kFeWaves = 8;
+constexpr int kFeGroup = 16;        // inputs per item
+constexpr int kFeWaves = 4;
 constexpr int kFeThreads = 64 * kFeWaves;
 constexpr int kFeInputsPerWave = kFeGroup / kFeWaves;
-constexpr int kFeBufStride = 17;                    // float2 per row of the pass-1 exchange (16 + 1 pad)
+constexpr int kFeWgsPerCu = 1;   // one wave per SIMD: 512 registers for coefficients, prefetch and FFT
+constexpr int kFeBufStride = 17;                    // float2 per row of the pass exchanges (16 + 1 pad)
 constexpr int kFeBufFloats = 2 * 64 * kFeBufStride;  // per wave: 64 rows
-constexpr int kFeCodeStride = 80;                   // bytes per channel row of the code tile (64 + pad)
+constexpr int kFeCodeStride = 20;                   // bytes per channel row of the code tile (16 + pad)
 
 // ---- twiddle tables, computed at compile time in double ----------------------
 
@@ -79,42 +86,22 @@ struct Table {
     float re[COUNT];
     float im[COUNT];
 };
-// W_N^e = exp(-2 pi i e / N)
-constexpr Table<1024> make_tw_pass1()
+// W_den^e = exp(-2 pi i e / den) for e < COUNT
+template <int COUNT>
+constexpr Table<COUNT> make_powers(long den)
 {
-    Table<1024> t{};
-    for (int l = 0; l < 64; ++l)
-        for (int k1 = 0; k1 < 16; ++k1) {
-            const SinCos v = sincos_turn((long)l * k1, 1024);
-            t.re[l * 16 + k1] = (float)v.c;
-            t.im[l * 16 + k1] = (float)-v.s;
-        }
-    return t;
-}
-constexpr Table<64> make_tw_pass2()
-{
-    Table<64> t{};
-    for (int m2 = 0; m2 < 4; ++m2)
-        for (int j1 = 0; j1 < 16; ++j1) {
-            const SinCos v = sincos_turn((long)m2 * j1, 64);
-            t.re[m2 * 16 + j1] = (float)v.c;
-            t.im[m2 * 16 + j1] = (float)-v.s;
-        }
-    return t;
-}
-constexpr Table<1024> make_tw_real()
-{
-    Table<1024> t{};
-    for (int c = 0; c < 1024; ++c) {
-        const SinCos v = sincos_turn(c, 2048);
-        t.re[c] = (float)v.c;
-        t.im[c] = (float)-v.s;
+    Table<COUNT> t{};
+    for (int e = 0; e < COUNT; ++e) {
+        const SinCos v = sincos_turn(e, den);
+        t.re[e] = (float)v.c;
+        t.im[e] = (float)-v.s;
     }
     return t;
 }
-__device__ constexpr Table<1024> kTwPass1 = make_tw_pass1();
-__device__ constexpr Table<64> kTwPass2 = make_tw_pass2();
-__device__ constexpr Table<1024> kTwReal = make_tw_real();
+__device__ constexpr Table<64> kW1024 = make_powers<64>(1024);   // pass-1 bases W1024^l
+__device__ constexpr Table<4> kW64 = make_powers<4>(64);         // pass-2 bases W64^m2
+__device__ constexpr Table<64> kW2048 = make_powers<64>(2048);   // real-unpack bases W2048^l
+constexpr Table<16> kW32 = make_powers<16>(32);                  // W2048^(64 v) = W32^v
 
 // ---- complex helpers ----------------------------------------------------------
 
@@ -125,6 +112,24 @@ __device__ __forceinline__ cf cadd(cf a, cf b) { return {a.r + b.r, a.i + b.i}; 
 __device__ __forceinline__ cf csub(cf a, cf b) { return {a.r - b.r, a.i - b.i}; }
 __device__ __forceinline__ cf cmul(cf a, cf b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
 __device__ __forceinline__ cf cmul_mi(cf a) { return {a.i, -a.r}; }   // a * (-i)
+
+// p[k] = w^k for k < 16: w, w^2, w^3 and w^4, w^8, w^12, then products
+// (each power at most three roundings from w)
+__device__ __forceinline__ void powers16(cf w, cf (&p)[16])
+{
+    p[0] = cf{1.f, 0.f};
+    p[1] = w;
+    p[2] = cmul(w, w);
+    p[3] = cmul(p[2], w);
+    p[4] = cmul(p[2], p[2]);
+    p[8] = cmul(p[4], p[4]);
+    p[12] = cmul(p[8], p[4]);
+#pragma unroll
+    for (int a = 4; a < 16; a += 4)
+#pragma unroll
+        for (int b = 1; b < 4; ++b)
+            p[a + b] = cmul(p[a], p[b]);
+}
 
 // forward 4-point DFT in place: x[k] = sum_n x[n] (-i)^{nk}
 __device__ __forceinline__ void dft4(cf &x0, cf &x1, cf &x2, cf &x3)
@@ -190,34 +195,73 @@ struct FeArgs {
     void *out;            // CODES: uint8 [n_spectra][1024][N]; else float2 [N][n_spectra][1024]
 };
 
-// One wave's FFT of one (input, spectrum): returns the 16 channel values
-// c = lane + 64 v (v < 16) of the real spectrum in y[v].
-__device__ __forceinline__ void fe_transform(const FeArgs &a, int input, int64_t m, const float2 (&hc)[kFeTaps][16],
+// Raw samples of one (input, spectrum) for this lane: 32 consecutive
+// samples x[(m + k) P + 32 lane + t] of each tap k, as two 16-byte loads.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+struct FeRaw {
+    u32x4 v[kFeTaps][2];
+};
+__device__ __forceinline__ void fe_load(const FeArgs &a, int input, int64_t m, FeRaw &r)
+{
+    const int lane = threadIdx.x & 63;
+    const u32x4 *x = (const u32x4 *)(a.adc + (int64_t)input * a.S + m * kFeP + 32 * lane);
+#pragma unroll
+    for (int k = 0; k < kFeTaps; ++k) {
+        r.v[k][0] = __builtin_nontemporal_load(x + k * (kFeP / 16));
+        r.v[k][1] = __builtin_nontemporal_load(x + k * (kFeP / 16) + 1);
+    }
+}
+
+__device__ __forceinline__ float byte_at(const u32x4 &v, int t)
+{
+    const uint32_t w = t < 4 ? v.x : t < 8 ? v.y : t < 12 ? v.z : v.w;
+    return (float)(int8_t)(w >> (8 * (t & 3)));
+}
+
+// One wave's FFT of one (input, spectrum) from its raw samples: returns the
+// 16 channel values c = lane + 64 v (v < 16) of the real spectrum in y[v].
+// hc[k][t] = h[k P + 32 lane + t].
+struct FeBases {
+    cf w1024, w64, w2048;   // W1024^lane, W64^(lane % 4), W2048^lane
+};
+__device__ __forceinline__ void fe_transform(const FeRaw &raw, const float (&hc)[kFeTaps][32], const FeBases &bs,
                                              float *buf, cf (&y)[16])
 {
     const int lane = threadIdx.x & 63;
-    // FIR: z[n] for n = 64 n1 + lane
+    // FIR on this lane's 32 samples -> z[n] for n = 16 lane + j
     cf z[16];
-    const int8_t *x = a.adc + (int64_t)input * a.S + m * kFeP + 2 * lane;
 #pragma unroll
-    for (int n1 = 0; n1 < 16; ++n1) {
+    for (int j = 0; j < 16; ++j) {
         float re = 0.f, im = 0.f;
 #pragma unroll
         for (int k = 0; k < kFeTaps; ++k) {
-            const short pair = *(const short *)(x + k * kFeP + 128 * n1);
-            re = fmaf(hc[k][n1].x, (float)(int8_t)(pair & 0xFF), re);
-            im = fmaf(hc[k][n1].y, (float)(int8_t)(pair >> 8), im);
+            re = fmaf(hc[k][2 * j], byte_at(raw.v[k][j >> 3], (2 * j) & 15), re);
+            im = fmaf(hc[k][2 * j + 1], byte_at(raw.v[k][j >> 3], (2 * j + 1) & 15), im);
         }
-        z[n1] = cf{re, im};
+        z[j] = cf{re, im};
     }
+    // exchange 0: z at n + n / 16, read back with stride 64 (n = 64 n1 + lane)
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+        *(float2 *)&buf[2 * (17 * lane + j)] = make_float2(z[j].r, z[j].i);
+    lds_sync();
+#pragma unroll
+    for (int n1 = 0; n1 < 16; ++n1) {
+        const float2 v = *(const float2 *)&buf[2 * (68 * n1 + lane + (lane >> 4))];
+        z[n1] = cf{v.x, v.y};
+    }
+    lds_sync();
     // pass 1: 16-point DFT over n1 (n = 64 n1 + l), twiddle W1024^{l k1}
     dft16(z);
+    {
+        cf tw[16];
+        powers16(bs.w1024, tw);
 #pragma unroll
-    for (int k1 = 0; k1 < 16; ++k1) {
-        const cf w{kTwPass1.re[lane * 16 + k1], kTwPass1.im[lane * 16 + k1]};
-        const cf v = cmul(z[k1], w);
-        // A[n2 = lane][k1] at row n2, column k1
-        *(float2 *)&buf[2 * (lane * kFeBufStride + k1)] = make_float2(v.r, v.i);
+        for (int k1 = 0; k1 < 16; ++k1) {
+            const cf v = cmul(z[k1], tw[k1]);
+            // A[n2 = lane][k1] at row n2, column k1
+            *(float2 *)&buf[2 * (lane * kFeBufStride + k1)] = make_float2(v.r, v.i);
+        }
     }
     lds_sync();
     // pass 2: lane = (k1, m2); 16-point DFT over m1 of A[4 m1 + m2][k1], twiddle W64^{m2 j1}
@@ -227,11 +271,15 @@ __device__ __forceinline__ void fe_transform(const FeArgs &a, int input, int64_t
         const float2 v = *(const float2 *)&buf[2 * ((4 * m1 + m2) * kFeBufStride + k1)];
         z[m1] = cf{v.x, v.y};
     }
-    dft16(z);
-#pragma unroll
-    for (int j1 = 0; j1 < 16; ++j1)
-        z[j1] = cmul(z[j1], cf{kTwPass2.re[m2 * 16 + j1], kTwPass2.im[m2 * 16 + j1]});
     lds_sync();
+    dft16(z);
+    {
+        cf tw[16];
+        powers16(bs.w64, tw);
+#pragma unroll
+        for (int j1 = 0; j1 < 16; ++j1)
+            z[j1] = cmul(z[j1], tw[j1]);
+    }
     // exchange: B[k1][m2][j1] at row 4 k1 + m2 (17-float2 rows), column j1
 #pragma unroll
     for (int j1 = 0; j1 < 16; ++j1)
@@ -255,7 +303,7 @@ __device__ __forceinline__ void fe_transform(const FeArgs &a, int input, int64_t
             Z[4 * u + j2] = b[j2];
     }
     lds_sync();
-    // Z in natural order k = k1 + 16 (r + 4 u) + 256 j2, stored at k + k / 16 (pad)
+    // Z in natural order k = k1 + 16 (r + 4 u) + 256 j2, stored at k + k / 16
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -264,7 +312,8 @@ __device__ __forceinline__ void fe_transform(const FeArgs &a, int input, int64_t
             *(float2 *)&buf[2 * (k + (k >> 4))] = make_float2(Z[4 * u + j2].r, Z[4 * u + j2].i);
         }
     lds_sync();
-    // real spectrum of channels c = lane + 64 v
+    // real spectrum of channels c = lane + 64 v: W2048^c = W2048^lane W32^v
+    const cf wl = bs.w2048;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
         const int c = lane + 64 * v;
@@ -273,7 +322,7 @@ __device__ __forceinline__ void fe_transform(const FeArgs &a, int input, int64_t
         const float2 q = *(const float2 *)&buf[2 * (cn + (cn >> 4))];
         const cf zc{p.x, p.y}, zn{q.x, -q.y};   // Z[c], conj Z[N - c]
         const cf e = cadd(zc, zn), d = csub(zc, zn);
-        const cf w{kTwReal.re[c], kTwReal.im[c]};
+        const cf w = v ? cmul(wl, cf{kW32.re[v], kW32.im[v]}) : wl;
         const cf od = cmul(w, d);                // W^c (Z[c] - Z*[N - c])
         // Y = e / 2 - i od / 2
         y[v] = cf{0.5f * (e.r + od.i), 0.5f * (e.i - od.r)};
@@ -285,57 +334,85 @@ template <bool CODES>
 __device__ __forceinline__ void fengine_body(uint8_t *smem, const FeArgs &a)
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    // work-group -> (spectrum, input group); spectra of one group are spread
-    // over the 8 XCDs in contiguous runs, so that the tap overlap between
-    // consecutive spectra hits the same L2
-    const int64_t groups = (a.N + kFeGroup - 1) / kFeGroup;
-    const int64_t per_xcd = (a.n_spectra * groups + 7) / 8;
-    const int64_t item = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-    if (item >= a.n_spectra * groups)
+    // items (spectrum m of input group g) in order m fastest; each XCD takes a
+    // contiguous run, so the taps shared by consecutive spectra meet in its L2
+    const int64_t groups = a.N / kFeGroup;
+    const int64_t items = a.n_spectra * groups;
+    const int64_t per_xcd = (items + 7) / 8;
+    const int64_t first = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    const int64_t end = min(items, (int64_t)((blockIdx.x & 7) + 1) * per_xcd);
+    const int64_t stride = gridDim.x >> 3;
+    if (first >= end)
         return;
-    const int64_t g = item / a.n_spectra, m = item % a.n_spectra;
-    const int i0 = (int)g * kFeGroup;
 
     float *buf = (float *)smem + w * kFeBufFloats;
     uint8_t *codes = smem + kFeWaves * kFeBufFloats * sizeof(float);
 
-    float2 hc[kFeTaps][16];
+    float hc[kFeTaps][32];
 #pragma unroll
     for (int k = 0; k < kFeTaps; ++k)
 #pragma unroll
-        for (int n1 = 0; n1 < 16; ++n1)
-            hc[k][n1] = *(const float2 *)(a.h + k * kFeP + 128 * n1 + 2 * lane);
-
-    for (int ii = 0; ii < kFeInputsPerWave; ++ii) {
-        const int input = i0 + w * kFeInputsPerWave + ii;
-        if (input >= a.N)
-            break;
-        cf y[16];
-        fe_transform(a, input, m, hc, buf, y);
-        if constexpr (CODES) {
-            const float *gi = a.gains + (int64_t)input * kFeN;
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int c = lane + 64 * v;
-                const float gv = gi[c];
-                const int re = quant4(gv * y[v].r), im = quant4(gv * y[v].i);
-                codes[c * kFeCodeStride + w * kFeInputsPerWave + ii] = (uint8_t)(((re & 15) << 4) | (im & 15));
-            }
-        } else {
-            float2 *o = (float2 *)a.out + ((int64_t)input * a.n_spectra + m) * kFeN;
-#pragma unroll
-            for (int v = 0; v < 16; ++v)
-                o[lane + 64 * v] = make_float2(y[v].r, y[v].i);
+        for (int t = 0; t < 32; t += 4) {
+            const float4 v = *(const float4 *)(a.h + k * kFeP + 32 * lane + t);
+            hc[k][t] = v.x;
+            hc[k][t + 1] = v.y;
+            hc[k][t + 2] = v.z;
+            hc[k][t + 3] = v.w;
         }
-    }
-    if constexpr (CODES) {
-        __syncthreads();
-        // rows of 64 codes (16 bytes per thread) to out[m][c][i0 ..]
-        uint8_t *o = (uint8_t *)a.out + (m * kFeN) * (int64_t)a.N + i0;
-        for (int t = threadIdx.x; t < kFeN * 4; t += kFeThreads) {
-            const int c = t >> 2, q = t & 3;
-            if (i0 + 16 * q < a.N)
-                *(uint4 *)(o + (int64_t)c * a.N + 16 * q) = *(const uint4 *)(codes + c * kFeCodeStride + 16 * q);
+
+    const FeBases bases{cf{kW1024.re[lane], kW1024.im[lane]}, cf{kW64.re[lane & 3], kW64.im[lane & 3]},
+                        cf{kW2048.re[lane], kW2048.im[lane]}};
+    // this wave's jobs: (item, ii) for items first, first + stride, ... and
+    // ii < 4; the next job's samples are loaded while the current one runs
+    auto input_of = [&](int64_t it, int ii) { return (int)(it / a.n_spectra) * kFeGroup + w * kFeInputsPerWave + ii; };
+    FeRaw raw;
+    fe_load(a, input_of(first, 0), first % a.n_spectra, raw);
+    for (int64_t it = first; it < end; it += stride) {
+        const int64_t m = it % a.n_spectra;
+        const int g = (int)(it / a.n_spectra);
+        for (int ii = 0; ii < kFeInputsPerWave; ++ii) {
+            const int input = g * kFeGroup + w * kFeInputsPerWave + ii;
+            const FeRaw cur = raw;
+            if (ii + 1 < kFeInputsPerWave)
+                fe_load(a, input + 1, m, raw);
+            else if (it + stride < end)
+                fe_load(a, input_of(it + stride, 0), (it + stride) % a.n_spectra, raw);
+            // this input's EQ gains, loaded before the transform so that
+            // their latency is hidden behind it
+            float gv16[16];
+            if constexpr (CODES) {
+                const float *gi = a.gains + (int64_t)input * kFeN;
+#pragma unroll
+                for (int v = 0; v < 16; ++v)
+                    gv16[v] = gi[lane + 64 * v];
+            }
+            cf y[16];
+            fe_transform(cur, hc, bases, buf, y);
+            if constexpr (CODES) {
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const int c = lane + 64 * v;
+                    const float gv = gv16[v];
+                    const int re = quant4(gv * y[v].r), im = quant4(gv * y[v].i);
+                    codes[c * kFeCodeStride + w * kFeInputsPerWave + ii] = (uint8_t)(((re & 15) << 4) | (im & 15));
+                }
+            } else {
+                float2 *o = (float2 *)a.out + ((int64_t)input * a.n_spectra + m) * kFeN;
+#pragma unroll
+                for (int v = 0; v < 16; ++v)
+                    o[lane + 64 * v] = make_float2(y[v].r, y[v].i);
+            }
+        }
+        if constexpr (CODES) {
+            __syncthreads();
+            // one 16-byte row per channel: out[m][c][16 g ..]
+            uint8_t *o = (uint8_t *)a.out + (m * kFeN) * (int64_t)a.N + g * kFeGroup;
+#pragma unroll
+            for (int c = threadIdx.x; c < kFeN; c += kFeThreads) {
+                const uint32_t *row = (const uint32_t *)(codes + c * kFeCodeStride);
+                *(uint4 *)(o + (int64_t)c * a.N) = make_uint4(row[0], row[1], row[2], row[3]);
+            }
+            __syncthreads();
         }
     }
 }
@@ -343,16 +420,30 @@ __device__ __forceinline__ void fengine_body(uint8_t *smem, const FeArgs &a)
 constexpr int kFeSmemCodes = kFeWaves * kFeBufFloats * 4 + kFeN * kFeCodeStride;
 constexpr int kFeSmemSpectra = kFeWaves * kFeBufFloats * 4;
 
-__global__ __launch_bounds__(kFeThreads) void xc_fengine_kernel(const FeArgs a)
+__global__ __launch_bounds__(kFeThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void xc_fengine_kernel(const FeArgs a)
 {
     __shared__ __attribute__((aligned(16))) uint8_t smem[kFeSmemCodes];
     fengine_body<true>(smem, a);
 }
 
-__global__ __launch_bounds__(kFeThreads) void xc_pfb_spectra_kernel(const FeArgs a)
+__global__ __launch_bounds__(kFeThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void xc_pfb_spectra_kernel(const FeArgs a)
 {
     __shared__ __attribute__((aligned(16))) uint8_t smem[kFeSmemSpectra];
     fengine_body<false>(smem, a);
+}
+
+// persistent grid: kFeWgsPerCu work-groups per compute unit, a multiple of 8
+// (one run of items per XCD), no more than there are items per XCD
+int fe_grid(int64_t items)
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 8)
+        cus = 256;
+    const int64_t per_xcd = (items + 7) / 8;
+    return 8 * (int)std::max<int64_t>(1, std::min<int64_t>(cus / 8 * kFeWgsPerCu, per_xcd));
 }
 
 int fe_check(const void *adc, int64_t S, int32_t N, const float *h, int64_t n_spectra, const void *out)
@@ -391,11 +482,11 @@ extern "C" int xcorr_fengine(const void *d_adc, int64_t n_samples, int32_t n_inp
         return rc;
     if (!d_gains || (uintptr_t)d_gains % 16)
         return XCORR_E_INVAL;
-    const int64_t items = n_spectra * ((n_inputs + kFeGroup - 1) / kFeGroup);
+    const int64_t items = n_spectra * (n_inputs / kFeGroup);
     if (items > (int64_t)1 << 30)
         return XCORR_E_INVAL;
     FeArgs a{(const int8_t *)d_adc, n_samples, n_inputs, d_coeffs, d_gains, n_spectra, d_out};
-    const int grid = (int)(8 * ((items + 7) / 8));
+    const int grid = fe_grid(items);
     hipLaunchKernelGGL(xc_fengine_kernel, dim3(grid), dim3(kFeThreads), 0, reinterpret_cast<hipStream_t>(stream), a);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? XCORR_OK : api_error(XCORR_E_HIP, std::string("fengine launch: ") + hipGetErrorString(e));
@@ -408,11 +499,11 @@ extern "C" int xcorr_pfb_spectra(const void *d_adc, int64_t n_samples, int32_t n
     int rc = fe_check(d_adc, n_samples, n_inputs, d_coeffs, n_spectra, d_out);
     if (rc)
         return rc;
-    const int64_t items = n_spectra * ((n_inputs + kFeGroup - 1) / kFeGroup);
+    const int64_t items = n_spectra * (n_inputs / kFeGroup);
     if (items > (int64_t)1 << 30)
         return XCORR_E_INVAL;
     FeArgs a{(const int8_t *)d_adc, n_samples, n_inputs, d_coeffs, nullptr, n_spectra, d_out};
-    const int grid = (int)(8 * ((items + 7) / 8));
+    const int grid = fe_grid(items);
     hipLaunchKernelGGL(xc_pfb_spectra_kernel, dim3(grid), dim3(kFeThreads), 0, reinterpret_cast<hipStream_t>(stream),
                        a);
     const hipError_t e = hipGetLastError();
