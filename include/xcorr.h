@@ -395,6 +395,41 @@ int xcorr_correlate_static(const xcorr_config *cfg, const void *d_volts, int64_t
                            int64_t *n_integrated, void *stream);
 
 /*
+ * Calibrator-noise-source gating aligned to integrations (paper Section 2.5,
+ * "CNS control module"): the CNS must switch on and off so that each
+ * on-window falls wholly inside one integration.  Sequence numbers are the
+ * block counters of xcorr_pipe / xcorr_reorder (the paper's MCNT, one per
+ * block); integration j covers [seq_origin + j * blocks_per_dump,
+ * seq_origin + (j + 1) * blocks_per_dump), as in xcorr_reorder.  Host only.
+ *
+ * xcorr_cns_plan_make: from the current sequence number `now` and a lead
+ * time `lead` (the host's latency for programming the F-engine), the CNS
+ * first switches on at first_on, the first integration start at or after
+ * now + lead; it stays on for on_blocks (1 .. blocks_per_dump) sequence
+ * numbers and repeats every period_dumps integrations (period_blocks
+ * sequence numbers): first_on and period_blocks are the two values the
+ * F-engine's counter block takes.  Errors: XCORR_E_INVAL for a NULL plan,
+ * blocks_per_dump or period_dumps outside [1, 2^30], on_blocks outside
+ * [1, blocks_per_dump], or a sequence number beyond 2^62.
+ * xcorr_cns_is_on: 1 if the CNS is on at sequence number seq, else 0.
+ * xcorr_cns_integration: 1 if integration j holds a CNS on-window (which
+ * then starts at its first block), else 0.
+ */
+typedef struct {
+    uint64_t seq_origin;
+    int64_t blocks_per_dump;
+    int64_t period_dumps;
+    int64_t on_blocks;
+    uint64_t first_on;          /* first sequence number with the CNS on */
+    int64_t first_integration;  /* the integration that starts at first_on */
+    int64_t period_blocks;      /* period_dumps * blocks_per_dump */
+} xcorr_cns_plan;
+int xcorr_cns_plan_make(uint64_t now, uint64_t lead, uint64_t seq_origin, int64_t blocks_per_dump,
+                        int64_t period_dumps, int64_t on_blocks, xcorr_cns_plan *out);
+int xcorr_cns_is_on(const xcorr_cns_plan *p, uint64_t seq);
+int xcorr_cns_integration(const xcorr_cns_plan *p, int64_t j);
+
+/*
  * F-engine front end (paper Section 2.2, "F-engine"): raw ADC samples ->
  * polyphase filter bank -> 1024 channels -> EQ -> 4+4-bit codes in the
  * X-engine's input order.  Fixed shape: 2048-point filter bank (real FFT,

@@ -28,7 +28,7 @@ ARCH = "gfx950"
 # (source, extra flags, object name).  The 8+8-bit MFMA kernels are compiled
 # once per diagonal block size so that the objects build in parallel.
 UNITS = [("xcorr_kernels.hip", [], "xcorr_kernels.o"), ("xcorr_api.cpp", [], "xcorr_api.o"),
-         ("xcorr_pipe.cpp", [], "xcorr_pipe.o"), ("xcorr_reorder.cpp", [], "xcorr_reorder.o"),
+         ("xcorr_pipe.cpp", [], "xcorr_pipe.o"), ("xcorr_reorder.cpp", [], "xcorr_reorder.o"), ("xcorr_cns.cpp", [], "xcorr_cns.o"),
          ("xcorr_mfma4.hip", [], "xcorr_mfma4.o"), ("xcorr_mfma4f.hip", [], "xcorr_mfma4f.o"),
          ("xcorr_batch.hip", [], "xcorr_batch.o"),
          ("xcorr_gauss4.hip", [], "xcorr_gauss4.o"), ("xcorr_static.hip", [], "xcorr_static.o"),

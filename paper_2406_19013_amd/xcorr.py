@@ -152,6 +152,9 @@ def load(path: str | None = None):
             "xcorr_plan_tile": [cfgp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                 ctypes.POINTER(ctypes.c_int32)],
             "xcorr_correlate_static": [cfgp, vp, i64, vp, ctypes.POINTER(i64), vp],
+            "xcorr_cns_plan_make": [u64, u64, u64, i64, i64, i64, vp],
+            "xcorr_cns_is_on": [vp, u64],
+            "xcorr_cns_integration": [vp, i64],
             "xcorr_pfb_prototype": [ctypes.c_int32, ctypes.c_int32, vp],
             "xcorr_fengine": [vp, i64, ctypes.c_int32, vp, vp, i64, vp, vp],
             "xcorr_pfb_spectra": [vp, i64, ctypes.c_int32, vp, i64, vp, vp],
@@ -473,6 +476,32 @@ def xcorr_correlate_static(cfg: Config, volts, n_samples: int, out, stream=None)
                                          ctypes.c_void_p(out.data_ptr()), ctypes.byref(n), _stream_handle(stream)),
            "xcorr_correlate_static")
     return n.value
+
+
+class CnsPlan(ctypes.Structure):
+    _fields_ = [
+        ("seq_origin", ctypes.c_uint64),
+        ("blocks_per_dump", ctypes.c_int64),
+        ("period_dumps", ctypes.c_int64),
+        ("on_blocks", ctypes.c_int64),
+        ("first_on", ctypes.c_uint64),
+        ("first_integration", ctypes.c_int64),
+        ("period_blocks", ctypes.c_int64),
+    ]
+
+    def is_on(self, seq: int) -> bool:
+        return bool(load().xcorr_cns_is_on(ctypes.byref(self), int(seq)))
+
+    def integration(self, j: int) -> bool:
+        return bool(load().xcorr_cns_integration(ctypes.byref(self), int(j)))
+
+
+def xcorr_cns_plan_make(now: int, lead: int, seq_origin: int, blocks_per_dump: int, period_dumps: int,
+                        on_blocks: int) -> CnsPlan:
+    p = CnsPlan()
+    _check(load().xcorr_cns_plan_make(int(now), int(lead), int(seq_origin), int(blocks_per_dump),
+                                      int(period_dumps), int(on_blocks), ctypes.byref(p)), "xcorr_cns_plan_make")
+    return p
 
 
 FE_POINTS, FE_CHANS, FE_TAPS = 2048, 1024, 4
