@@ -288,6 +288,52 @@ def bench_fengine(dev, stream, reps: int) -> dict:
             "end_to_end_ms": e2e_ms, "end_to_end_rtf": span_s / (e2e_ms / 1e3)}
 
 
+def bench_linearity(dev) -> dict:
+    """Output power against input power through the GPU F- and X-engines on
+    synthetic data: 8 pairs of inputs sharing a common noise signal (rho =
+    0.5), ADC noise of 16 * 10^(L/20) codes for L = -30 .. +10 dB, fixed EQ
+    gains; the response is the pairs' mean cross power over channels
+    100 .. 900, and the linear range is where it stays within 1 dB of
+    proportionality through the 0 dB point."""
+    import numpy as np
+    import torch
+
+    from paper_2406_19013_amd import synth
+    from paper_2406_19013_amd import xcorr as X
+
+    N, M, P, F = 16, 64, X.FE_POINTS, X.FE_CHANS
+    S = (M + X.FE_TAPS - 1) * P
+    h = torch.from_numpy(X.xcorr_pfb_prototype()).to(dev)
+    gains = torch.full((N, F), synth.FE_EQ_BASE, dtype=torch.float32, device=dev)
+    codes = torch.empty((M, F, N), dtype=torch.uint8, device=dev)
+    c = X.Correlator(N, F, 4, X.PATH_I8_MFMA, device=dev)
+    g = torch.Generator(device=dev).manual_seed(synth.seed_of(synth.BASE_SEED, 80, 0))
+    common = torch.randn((N // 2, S), generator=g, device=dev)
+    own = torch.randn((N, S), generator=g, device=dev)
+    pairs = np.array([(2 * k + 1) * (2 * k + 2) // 2 + 2 * k for k in range(N // 2)])
+    levels = np.arange(-30, 12, 2.0)
+    resp = []
+    for db in levels:
+        sigma = synth.FE_ADC_SIGMA * 10 ** (db / 20)
+        x = (common.repeat_interleave(2, 0) + own) * (sigma / np.sqrt(2))
+        adc = torch.clamp(torch.round(x), -128, 127).to(torch.int8)
+        X.xcorr_fengine(adc, h, gains, codes, M)
+        vis, _, _ = c.ingest_dump(codes)
+        resp.append(float(vis.double().cpu().numpy()[100:900][:, pairs, 0].mean()))
+    c.close()
+    ydb = 10 * np.log10(np.maximum(np.array(resp), 1e-12))
+    dev_db = ydb - (ydb[levels == 0][0] + levels)
+    i0 = int(np.where(levels == 0)[0][0])
+    lo = hi = i0
+    while lo > 0 and abs(dev_db[lo - 1]) <= 1.0:
+        lo -= 1
+    while hi + 1 < len(levels) and abs(dev_db[hi + 1]) <= 1.0:
+        hi += 1
+    return {"workload": "linearity-16in-64spectra-noise-pairs", "levels_db": levels.tolist(),
+            "deviation_db": [round(float(d), 2) for d in dev_db],
+            "linear_range_db": [float(levels[lo]), float(levels[hi])], "linear_span_db": float(levels[hi] - levels[lo])}
+
+
 def bench_streaming(dev, n_blocks: int, paced_blocks: int, concurrent_blocks: int) -> dict:
     """1024-sample blocks of 4096 channels (33.55 ms of data each), a dump
     every 128 blocks: the 192-input stream device-resident (unpaced) and from
@@ -638,6 +684,8 @@ def main():
         _progress("streaming workload done")
         result["fengine"] = bench_fengine(dev, stream, max(5, args.steps // 2))
         _progress("F-engine workload done")
+        result["linearity"] = bench_linearity(dev)
+        _progress("linearity sweep done")
         result["latency_ms"]["p99_block_stream"] = result["streaming"]["n192_device_unpaced"]["p99_ms"]
     if not args.no_cpu:
         with torch.cuda.stream(stream):

@@ -467,6 +467,22 @@ int xcorr_pfb_spectra(const void *d_adc, int64_t n_samples, int32_t n_inputs, co
                       int64_t n_spectra, void *d_out, void *stream);
 
 /*
+ * Full-Stokes visibilities of dual-polarisation feeds (paper Section 1:
+ * full-Stokes output; Section 3.3: polarisations X north-south and Y
+ * east-west).  d_vis holds a dump of N = 2 Nf inputs, int32 [F][P][2]
+ * (xcorr_dump's layout), input 2 f + pol being feed f's polarisation pol
+ * (0 = X, 1 = Y).  For feeds a >= b, with XX = V(2a, 2b), YY = V(2a+1, 2b+1),
+ * XY = V(2a, 2b+1) (conj V(2a+1, 2a) when a = b) and YX = V(2a+1, 2b):
+ * I = XX + YY, Q = XX - YY, U = XY + YX, V = -i (XY - YX), written exactly
+ * as int64 (re, im) to d_out [F][Nf (Nf + 1) / 2][4][2], feed pair
+ * a (a + 1) / 2 + b, Stokes order I, Q, U, V.  Async on `stream`; buffers
+ * caller-owned.  Errors: XCORR_E_INVAL for an odd or < 2 input count,
+ * n_chans outside [1, 65535], NULL or misaligned pointers (d_vis 8 bytes,
+ * d_out 16 bytes); XCORR_E_HIP if the launch fails.
+ */
+int xcorr_stokes(const void *d_vis, int32_t n_inputs, int32_t n_chans, void *d_out, void *stream);
+
+/*
  * Hardware ceilings for the roofline of a benchmark (no correlation is
  * computed).  Enqueued on `stream`; the caller times them with events.
  *   XCORR_CEILING_MFMA_I8: one work-group of 8 waves per compute unit (two

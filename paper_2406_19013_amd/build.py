@@ -33,7 +33,8 @@ UNITS = [("xcorr_kernels.hip", [], "xcorr_kernels.o"), ("xcorr_api.cpp", [], "xc
          ("xcorr_batch.hip", [], "xcorr_batch.o"),
          ("xcorr_gauss4.hip", [], "xcorr_gauss4.o"), ("xcorr_static.hip", [], "xcorr_static.o"),
          ("xcorr_ceiling.hip", [], "xcorr_ceiling.o"),
-         ("xcorr_fengine.hip", [], "xcorr_fengine.o")] + [
+         ("xcorr_fengine.hip", [], "xcorr_fengine.o"),
+         ("xcorr_stokes.hip", [], "xcorr_stokes.o")] + [
     ("xcorr_mfma8.hip", [f"-DXC_D={d}"], f"xcorr_mfma8_d{d}.o") for d in range(1, 7)]
 RESOURCES = "kernel_resources.txt"
 

@@ -155,6 +155,7 @@ def load(path: str | None = None):
             "xcorr_cns_plan_make": [u64, u64, u64, i64, i64, i64, vp],
             "xcorr_cns_is_on": [vp, u64],
             "xcorr_cns_integration": [vp, i64],
+            "xcorr_stokes": [vp, ctypes.c_int32, ctypes.c_int32, vp, vp],
             "xcorr_pfb_prototype": [ctypes.c_int32, ctypes.c_int32, vp],
             "xcorr_fengine": [vp, i64, ctypes.c_int32, vp, vp, i64, vp, vp],
             "xcorr_pfb_spectra": [vp, i64, ctypes.c_int32, vp, i64, vp, vp],
@@ -476,6 +477,19 @@ def xcorr_correlate_static(cfg: Config, volts, n_samples: int, out, stream=None)
                                          ctypes.c_void_p(out.data_ptr()), ctypes.byref(n), _stream_handle(stream)),
            "xcorr_correlate_static")
     return n.value
+
+
+def xcorr_stokes(vis, n_inputs: int, out=None, stream=None):
+    """Full-Stokes visibilities int64 [F][Nf (Nf + 1) / 2][4][2] from a dump
+    vis int32 [F][P][2] of n_inputs = 2 Nf inputs."""
+    import torch
+    F = vis.shape[0]
+    nf = n_inputs // 2
+    if out is None:
+        out = torch.empty((F, nf * (nf + 1) // 2, 4, 2), dtype=torch.int64, device=vis.device)
+    _check(load().xcorr_stokes(ctypes.c_void_p(vis.data_ptr()), int(n_inputs), int(F), ctypes.c_void_p(out.data_ptr()),
+                               _stream_handle(stream)), "xcorr_stokes")
+    return out
 
 
 class CnsPlan(ctypes.Structure):
