@@ -49,6 +49,21 @@ constexpr int g3_ntiles(int D) { return D * (D + 1) / 2; }
 constexpr bool g3_diag(int t) { return tri_I(t) == tri_J(t); }
 constexpr int g3_abs(int x) { return x < 0 ? -x : x; }
 
+// Region geometry.  A triangle of D blocks: local blocks 0 .. D-1, tiles
+// (I, J <= I) in row-major order.  A D x D rectangle below the diagonal
+// (D <= 4): local row blocks 0 .. D-1 and column blocks D .. 2D-1, tile t =
+// (t / D, D + t % D), no diagonal tiles.
+template <bool RECT>
+constexpr int g3_tiles(int D) { return RECT ? D * D : D * (D + 1) / 2; }
+template <bool RECT>
+constexpr int g3_blocks(int D) { return RECT ? 2 * D : D; }
+template <bool RECT>
+constexpr int g3_row(int D, int t) { return RECT ? t / D : tri_I(t); }
+template <bool RECT>
+constexpr int g3_col(int D, int t) { return RECT ? D + t % D : tri_J(t); }
+template <bool RECT>
+constexpr bool g3_isdiag(int D, int t) { return !RECT && tri_I(t) == tri_J(t); }
+
 // Waves per work-group: two per SIMD, 256 registers each.
 #ifndef XC_G3_WAVES
 #define XC_G3_WAVES 8
@@ -61,13 +76,15 @@ constexpr int kG3Threads = 64 * kG3Waves;
 constexpr int kG3MaxWaves = 16;
 struct G3Split {
     uint32_t mask[kG3MaxWaves];
-    int sum_owner[6];   // wave slot that sums the forms of block b
+    int sum_owner[8];   // wave slot that sums the forms of local block b
 };
-constexpr int g3_units(int t) { return g3_diag(t) ? 2 : 3; }
-constexpr bool g3_touches(uint32_t mask, int b)
+template <bool RECT>
+constexpr int g3_units(int D, int t) { return g3_isdiag<RECT>(D, t) ? 2 : 3; }
+template <bool RECT>
+constexpr bool g3_touches(int D, uint32_t mask, int b)
 {
-    for (int t = 0; t < 21; ++t)
-        if ((mask >> t & 1) && (tri_I(t) == b || tri_J(t) == b))
+    for (int t = 0; t < g3_tiles<RECT>(D); ++t)
+        if ((mask >> t & 1) && (g3_row<RECT>(D, t) == b || g3_col<RECT>(D, t) == b))
             return true;
     return false;
 }
@@ -77,13 +94,14 @@ constexpr bool g3_touches(uint32_t mask, int b)
 // per diagonal tile) is closest to k/W of the total; segments go to SIMDs
 // largest first, each to the SIMD with the least MFMA work so far; the sums
 // of a block go to the least-loaded wave that reads it.
+template <bool RECT>
 constexpr G3Split g3_contiguous_split(int D, int W)
 {
     G3Split sp{};
-    const int NT = g3_ntiles(D);
+    const int NT = g3_tiles<RECT>(D);
     int cum[6 * 7 / 2 + 1] = {};
     for (int t = 0; t < NT; ++t)
-        cum[t + 1] = cum[t] + g3_units(t);
+        cum[t + 1] = cum[t] + g3_units<RECT>(D, t);
     const int U = cum[NT];
     int bound[kG3MaxWaves + 1] = {};
     for (int k = 1; k < W; ++k) {
@@ -116,10 +134,10 @@ constexpr G3Split g3_contiguous_split(int D, int W)
             sp.mask[slot] |= 1u << t;
         units[slot] = su[k];
     }
-    for (int b = 0; b < D; ++b) {
+    for (int b = 0; b < g3_blocks<RECT>(D); ++b) {
         int best = -1;
         for (int s = 0; s < W; ++s)
-            if (g3_touches(sp.mask[s], b) && (best < 0 || units[s] < units[best]))
+            if (g3_touches<RECT>(D, sp.mask[s], b) && (best < 0 || units[s] < units[best]))
                 best = s;
         sp.sum_owner[b] = best;
         if (best >= 0)
@@ -137,61 +155,65 @@ constexpr G3Split g3_contiguous_split(int D, int W)
 //          6 {(5,1) (5,5)}  7 {(2,1) (3,2) (3,3)}
 //   D = 5: slot 0 {(4,2)}  1 {(4,3) (4,4)}  2 {(1,0) (1,1)}  3 {(0,0) (4,0)}
 //          4 {(3,0) (3,3)}  5 {(2,2) (3,2)}  6 {(2,0) (2,1)}  7 {(3,1) (4,1)}
+template <bool RECT>
 constexpr G3Split g3_make_split(int D, int W)
 {
-    if (W == 8 && D == 6)
-        return G3Split{{0x804, 0x1020, 0xc2000, 0x4401, 0x28008, 0xc2, 0x110000, 0x310}, {3, 0, 1, 2, 0, 6}};
-    if (W == 8 && D == 5)
-        return G3Split{{0x1000, 0x6000, 0x6, 0x401, 0x240, 0x120, 0x18, 0x880}, {4, 2, 5, 1, 0, -1}};
-    return g3_contiguous_split(D, W);
+    if (!RECT && W == 8 && D == 6)
+        return G3Split{{0x804, 0x1020, 0xc2000, 0x4401, 0x28008, 0xc2, 0x110000, 0x310}, {3, 0, 1, 2, 0, 6, -1, -1}};
+    if (!RECT && W == 8 && D == 5)
+        return G3Split{{0x1000, 0x6000, 0x6, 0x401, 0x240, 0x120, 0x18, 0x880}, {4, 2, 5, 1, 0, -1, -1, -1}};
+    return g3_contiguous_split<RECT>(D, W);
 }
-template <int D>
-constexpr G3Split kG3Split = g3_make_split(D, kG3Waves);
+template <int D, bool RECT>
+constexpr G3Split kG3Split = g3_make_split<RECT>(D, kG3Waves);
 
-template <int D>
-constexpr uint32_t g3_mask(int s) { return kG3Split<D>.mask[s]; }
-template <int D>
-constexpr bool g3_has(int s, int t) { return t < 32 && (g3_mask<D>(s) >> t & 1); }
+template <int D, bool RECT>
+constexpr uint32_t g3_mask(int s) { return kG3Split<D, RECT>.mask[s]; }
+template <int D, bool RECT>
+constexpr bool g3_has(int s, int t) { return t < 32 && (g3_mask<D, RECT>(s) >> t & 1); }
 // position of tile t among the tiles of slot s (its accumulator index)
-template <int D>
+template <int D, bool RECT>
 constexpr int g3_rank(int s, int t)
 {
     int r = 0;
     for (int u = 0; u < t; ++u)
-        r += g3_has<D>(s, u);
+        r += g3_has<D, RECT>(s, u);
     return r;
 }
-template <int D>
-constexpr int g3_ntiles_of(int s) { return g3_rank<D>(s, g3_ntiles(D)); }
-template <int D>
-constexpr bool g3_uses_block(int s, int b) { return g3_touches(g3_mask<D>(s), b); }
-template <int D>
+template <int D, bool RECT>
+constexpr int g3_ntiles_of(int s) { return g3_rank<D, RECT>(s, g3_tiles<RECT>(D)); }
+template <int D, bool RECT>
+constexpr bool g3_uses_block(int s, int b) { return g3_touches<RECT>(D, g3_mask<D, RECT>(s), b); }
+template <int D, bool RECT>
 constexpr bool g3_owns_sums(int s, int b)
 {
-    return kG3Split<D>.sum_owner[b] == s;
+    return kG3Split<D, RECT>.sum_owner[b] == s;
 }
 // Order in which a wave unpacks its blocks within a K step: greedily the
 // block that completes the most MFMA work with the blocks already unpacked
 // (ties: the lower block), so that MFMAs start early and the later blocks'
 // unpacking runs under them.  pos < 0 for a block the wave does not read.
-template <int D>
+template <int D, bool RECT>
 constexpr int g3_block_pos(int s, int b)
 {
-    if (!g3_uses_block<D>(s, b))
+    constexpr int NB = g3_blocks<RECT>(D);
+    if (!g3_uses_block<D, RECT>(s, b))
         return -1;
-    bool done[6] = {};
-    for (int p = 0; p < D; ++p) {
+    bool done[8] = {};
+    for (int p = 0; p < NB; ++p) {
         int best = -1, best_gain = -1;
-        for (int c = 0; c < D; ++c) {
-            if (done[c] || !g3_uses_block<D>(s, c))
+        for (int c = 0; c < NB; ++c) {
+            if (done[c] || !g3_uses_block<D, RECT>(s, c))
                 continue;
             int gain = 0;
-            for (int t = 0; t < g3_ntiles(D); ++t)
-                if (g3_has<D>(s, t) && (tri_I(t) == c || tri_J(t) == c)) {
-                    const int o = tri_I(t) == c ? tri_J(t) : tri_I(t);
+            for (int t = 0; t < g3_tiles<RECT>(D); ++t) {
+                const int r = g3_row<RECT>(D, t), k = g3_col<RECT>(D, t);
+                if (g3_has<D, RECT>(s, t) && (r == c || k == c)) {
+                    const int o = r == c ? k : r;
                     if (o == c || done[o])
-                        gain += g3_units(t);
+                        gain += g3_units<RECT>(D, t);
                 }
+            }
             if (gain > best_gain) {
                 best = c;
                 best_gain = gain;
@@ -204,19 +226,19 @@ constexpr int g3_block_pos(int s, int b)
     return -1;
 }
 // a tile's MFMAs go right after the later of its two blocks is unpacked
-template <int D>
+template <int D, bool RECT>
 constexpr int g3_tile_pos(int s, int t)
 {
-    const int a = g3_block_pos<D>(s, tri_I(t)), b = g3_block_pos<D>(s, tri_J(t));
+    const int a = g3_block_pos<D, RECT>(s, g3_row<RECT>(D, t)), b = g3_block_pos<D, RECT>(s, g3_col<RECT>(D, t));
     return a > b ? a : b;
 }
-template <int D>
+template <int D, bool RECT>
 constexpr int g3_mfmas_of(int s)
 {
     int n = 0;
-    for (int t = 0; t < g3_ntiles(D); ++t)
-        if (g3_has<D>(s, t))
-            n += g3_units(t);
+    for (int t = 0; t < g3_tiles<RECT>(D); ++t)
+        if (g3_has<D, RECT>(s, t))
+            n += g3_units<RECT>(D, t);
     return n;
 }
 
@@ -225,20 +247,29 @@ constexpr int g3_diag_slot(int t) { return tri_I(t); }
 
 // ---- resources ---------------------------------------------------------------
 
-constexpr int g3_wgs_per_cu(int D) { return D <= 3 ? 2 : 1; }
+// two work-groups per CU for small triangles (128 registers per wave); a
+// rectangle's 2D blocks of operands need the full 256
+template <bool RECT>
+constexpr int g3_wgs_per_cu(int D) { return !RECT && D <= 3 ? 2 : 1; }
 // waves of this kernel per SIMD
-constexpr int g3_waves_per_eu(int D) { return g3_wgs_per_cu(D) * kG3Waves / 4; }
-constexpr int g3_nbuf(int D) { return D <= 3 ? 4 : 8; }
+template <bool RECT>
+constexpr int g3_waves_per_eu(int D) { return g3_wgs_per_cu<RECT>(D) * kG3Waves / 4; }
+template <bool RECT>
+constexpr int g3_nbuf(int D) { return g3_wgs_per_cu<RECT>(D) == 2 ? 4 : 8; }
 constexpr int kG3Chunk = 64;                             // time rows per ring slot
 #ifndef XC_G3_CPB
 #define XC_G3_CPB 2
 #endif
 constexpr int kG3ChunksPerBarrier = XC_G3_CPB;             // chunks per work-group barrier
 constexpr int kG3TileStride = 33;                        // ints per row of a transpose tile
-constexpr int g3_ring_bytes(int D) { return g3_nbuf(D) * kG3Chunk * kRowBytes; }
-constexpr int g3_tr_bytes(int D) { return D * 32 * kG3TileStride * 4; }
-constexpr int g3_gh_bytes(int D) { return D * 32 * 8; }
-constexpr int g3_smem_bytes(int D) { return g3_ring_bytes(D) + g3_tr_bytes(D) + g3_gh_bytes(D); }
+template <bool RECT>
+constexpr int g3_ring_bytes(int D) { return g3_nbuf<RECT>(D) * kG3Chunk * kRowBytes; }
+template <bool RECT>
+constexpr int g3_tr_bytes(int D) { return RECT ? 0 : D * 32 * kG3TileStride * 4; }
+template <bool RECT>
+constexpr int g3_gh_bytes(int D) { return g3_blocks<RECT>(D) * 32 * 8; }
+template <bool RECT>
+constexpr int g3_smem_bytes(int D) { return g3_ring_bytes<RECT>(D) + g3_tr_bytes<RECT>(D) + g3_gh_bytes<RECT>(D); }
 
 // LDS-only wait: outstanding LDS operations of this wave done, memory
 // operations in flight left alone (vmcnt and expcnt at their maxima).
@@ -256,28 +287,49 @@ struct G3Args {
     const uint8_t *volts;   // [T][F][N] packed (MB = 0)
     int64_t T;              // samples (MB = 1: n_blocks * cpb * 64)
     int F, N;
-    int per;                // channels per XCD range
+    int nreg;               // regions of this launch's shape per channel
+    int per;                // items (channel, region) per XCD range
     int2 *out;              // [F][P] results
     const int2 *in;         // [F][P] running sums (ACC = 1)
 };
 
+// First global block of a region's rows and of its columns: triangle r of a
+// channel starts at block D r; rectangle k (k-th pair a > b in row-major
+// order) has rows from segment a and columns from segment b.
+template <int D, bool RECT>
+__device__ __forceinline__ void g3_region_origin(int r, int &rb, int &cb)
+{
+    if constexpr (!RECT) {
+        rb = cb = D * r;
+    } else {
+        int a = (int)((1.f + sqrtf(1.f + 8.f * r)) * 0.5f);
+        while (a * (a - 1) / 2 > r)
+            --a;
+        while ((a + 1) * a / 2 <= r)
+            ++a;
+        rb = D * a;
+        cb = D * (r - a * (a - 1) / 2);
+    }
+}
+
 // One wave's share of a launch: its tiles of every channel item of its
 // work-group, K loop over the continuous chunk stream, and the epilogue of
 // each item.
-template <int D, int SLOT, int ACC, int MB>
+template <int D, bool RECT, int SLOT, int ACC, int MB>
 __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const BlockTable *bt,
                                         const uint8_t *__restrict__ volts)
 {
-    constexpr int NBUF = g3_nbuf(D);
+    constexpr int NBUF = g3_nbuf<RECT>(D);
     constexpr int KC = kG3Chunk;
     constexpr int BUF = KC * kRowBytes;
     constexpr int LOADS = KC * 16 / kG3Threads;         // 16-byte DMA units per lane per chunk
-    constexpr int NTT = g3_ntiles(D);
-    constexpr int NT = g3_ntiles_of<D>(SLOT) > 0 ? g3_ntiles_of<D>(SLOT) : 1;
+    constexpr int NTT = g3_tiles<RECT>(D);
+    constexpr int NB = g3_blocks<RECT>(D);
+    constexpr int NT = g3_ntiles_of<D, RECT>(SLOT) > 0 ? g3_ntiles_of<D, RECT>(SLOT) : 1;
 
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
-    if constexpr (g3_waves_per_eu(D) == 1) {
+    if constexpr (g3_waves_per_eu<RECT>(D) == 1) {
         // an AGPR operand in the function makes the compiler take the MFMA
         // forms that accumulate in AGPRs (with one wave per SIMD it then
         // has 256 of each)
@@ -287,13 +339,14 @@ __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const Bl
     const int lane = tid & 63;
     const int g = lane >> 4, q = lane & 15;
     lds_u8 *const ring = (lds_u8 *)smem;
-    int *const trs = (int *)(smem + g3_ring_bytes(D));                        // transpose tiles
-    int *const gh = (int *)(smem + g3_ring_bytes(D) + g3_tr_bytes(D));       // g, h per input
+    int *const trs = (int *)(smem + g3_ring_bytes<RECT>(D));                             // transpose tiles
+    int *const gh = (int *)(smem + g3_ring_bytes<RECT>(D) + g3_tr_bytes<RECT>(D));      // g, h per local input
 
-    // this work-group's channels: the local items m, m + M, ... of its XCD's range
+    // this work-group's items (channel, region): the local items m, m + M, ...
+    // of its XCD's range of consecutive items
     const int xcd = blockIdx.x & 7, m = blockIdx.x >> 3, M = gridDim.x >> 3;
     const int r0 = xcd * a.per;
-    const int rlen = min(a.per, a.F - r0);
+    const int rlen = min(a.per, a.F * a.nreg - r0);
     const int n_my = rlen > m ? (rlen - m + M - 1) / M : 0;
     const int nch = (int)((a.T + KC - 1) / KC);
     const int total = n_my * nch;
@@ -304,31 +357,36 @@ __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const Bl
     const int Tp = nch * KC;
 
     // DMA share of this wave: unit U = (SLOT * LOADS + k) * 64 + lane of a
-    // chunk -> time row U / 16, position U % 16 (swizzled unit p); the lane
-    // offsets of channel f (recomputed when the issue pointer reaches the
-    // next channel, so nothing is held across the K loop for it)
-    auto dma_offset = [&](int k, int f) {
+    // chunk -> time row U / 16, position U % 16 (swizzled unit p); units
+    // 0 .. 2D-1 hold the region's row blocks, 2D .. 4D-1 (rectangles) its
+    // column blocks; the lane offsets of an item are recomputed when the
+    // issue pointer reaches it, so nothing is held across the K loop for them
+    auto dma_offset = [&](int k, int f, int rb, int cb) {
         const int U = (SLOT * LOADS + k) * 64 + lane;
         const int r = U >> 4;
         const int p = (U & 15) ^ ((r & 7) << 1);
-        return p < 2 * D && 16 * p < a.N ? (int)(r * row_bytes) + f * a.N + 16 * p : kBufferOutOfRange;
+        const int byte = p < 2 * D ? 32 * rb + 16 * p : 32 * cb + 16 * (p - 2 * D);
+        return p < 2 * NB && byte < a.N ? (int)(r * row_bytes) + f * a.N + byte : kBufferOutOfRange;
     };
     // operand read offsets (see frag_tr8): row (g >> 1) * 16 + (q >> 1) of the
     // K step, unit 2b + (g & 1) swizzled
     const int row_off = ((g >> 1) * 16 + (q >> 1)) * kRowBytes + (q & 1) * 8;
-    int colo[D];
+    int colo[NB];
 #pragma unroll
-    for (int b = 0; b < D; ++b)
+    for (int b = 0; b < NB; ++b)
         colo[b] = ((2 * b + (g & 1)) ^ (q & 14)) << 4;
 
     // issue state (wave-uniform): item and chunk of the next chunk to issue
     int is_k = 0, is_c = 0;
     int voff[LOADS];
     auto set_issue_item = [&](int k) {
-        const int f = r0 + m + k * M;
+        const int it = r0 + m + k * M;
+        const int f = it / a.nreg;
+        int rb, cb;
+        g3_region_origin<D, RECT>(it - f * a.nreg, rb, cb);
 #pragma unroll
         for (int u = 0; u < LOADS; ++u)
-            voff[u] = dma_offset(u, f);
+            voff[u] = dma_offset(u, f, rb, cb);
     };
     set_issue_item(0);
     auto issue_next = [&](int bufi) {
@@ -361,14 +419,14 @@ __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const Bl
     // per-input sums of the owned blocks, as unsigned byte SADs (two chains
     // each): sz = sum of X ^ 0x88 (16 (re + 8) + im + 8 per sample), sl =
     // sum of |A - R| (im + 8 per sample: A and R share the high nibble)
-    int sz[D], sl[D], sz2[D], sl2[D];
+    int sz[NB], sl[NB], sz2[NB], sl2[NB];
     auto clear = [&]() {
         static_for<0, NT>([&](auto tc) {
             acc_ab[tc] = v16i{};
             acc_ba[tc] = v16i{};
             acc_rr[tc] = v16i{};
         });
-        static_for<0, D>([&](auto bc) {
+        static_for<0, NB>([&](auto bc) {
             sz[bc] = 0;
             sl[bc] = 0;
             sz2[bc] = 0;
@@ -382,18 +440,22 @@ __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const Bl
     // unpacked into the other register set.  raw: the packed bytes of a step;
     // A, B, R: its three forms; the owner of a block also sums its forms.
     auto read_step = [&](lds_u8 *cb, int koff, v4i *X) {
-        static_for<0, D>([&](auto bc) {
+        static_for<0, NB>([&](auto bc) {
             constexpr int b = bc;
-            if constexpr (g3_uses_block<D>(SLOT, b))
+            if constexpr (g3_uses_block<D, RECT>(SLOT, b))
                 X[b] = frag_tr8<8 * kRowBytes>(cb + colo[b] + koff);
         });
     };
-    // epilogue of one channel: combine, descale and store this wave's tiles
-    auto epilogue = [&](int f) {
+    // epilogue of one item (channel, region): combine, descale and store this
+    // wave's tiles
+    auto epilogue = [&](int it) {
+        const int f = it / a.nreg;
+        int rb, cb;
+        g3_region_origin<D, RECT>(it - f * a.nreg, rb, cb);
         // per-input sums: lanes l and l + 32 hold the two K halves of input l % 32
-        static_for<0, D>([&](auto bc) {
+        static_for<0, NB>([&](auto bc) {
             constexpr int b = bc;
-            if constexpr (g3_owns_sums<D>(SLOT, b)) {
+            if constexpr (g3_owns_sums<D, RECT>(SLOT, b)) {
                 const int szl = sz[b] + sz2[b], sll = sl[b] + sl2[b];
                 const uint32_t szt = (uint32_t)(szl + __shfl_xor(szl, 32));
                 const uint32_t slt = (uint32_t)(sll + __shfl_xor(sll, 32));
@@ -414,12 +476,14 @@ __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const Bl
         const int il0 = 4 * (lane >> 5);
         static_for<0, NTT>([&](auto tc) {
             constexpr int t = tc;
-            if constexpr (g3_has<D>(SLOT, t)) {
-            constexpr int q = g3_rank<D>(SLOT, t);
-            constexpr int I = tri_I(t), J = tri_J(t);
-            constexpr bool diag = g3_diag(t);
-            const int j = J * 32 + jl;
-            const int2 ghj = *(const int2 *)&gh[j * 2];
+            if constexpr (g3_has<D, RECT>(SLOT, t)) {
+            constexpr int q = g3_rank<D, RECT>(SLOT, t);
+            constexpr int I = g3_row<RECT>(D, t), J = g3_col<RECT>(D, t);   // local blocks
+            constexpr bool diag = g3_isdiag<RECT>(D, t);
+            // column input: local index for the sums, global for the output
+            const int jloc = J * 32 + jl;
+            const int j = (RECT ? cb + (J - D) : rb + J) * 32 + jl;
+            const int2 ghj = *(const int2 *)&gh[jloc * 2];
             v16i ba;
             if constexpr (diag) {
                 // P_ba of a diagonal tile is the transpose of its P_ab
@@ -435,7 +499,8 @@ __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const Bl
             }
 #pragma unroll
             for (int r4 = 0; r4 < 4; ++r4) {
-                const int ib = I * 32 + 8 * r4 + il0;     // rows ib .. ib + 3
+                const int ibl = I * 32 + 8 * r4 + il0;    // rows ibl .. ibl + 3 (local)
+                const int ib = rb * 32 + ibl;             // and their global inputs
                 // running sums of these rows (ACC = 1), from a valid address
                 // where the pair does not exist
                 int2 old[4];
@@ -447,8 +512,8 @@ __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const Bl
                         old[u] = in_f[ok ? (int64_t)i * (i + 1) / 2 + j : 0];
                     }
                 }
-                const int4 ghi01 = *(const int4 *)&gh[ib * 2];
-                const int4 ghi23 = *(const int4 *)&gh[ib * 2 + 4];
+                const int4 ghi01 = *(const int4 *)&gh[ibl * 2];
+                const int4 ghi23 = *(const int4 *)&gh[ibl * 2 + 4];
                 const int gi[4] = {ghi01.x, ghi01.z, ghi23.x, ghi23.z};
                 const int hi[4] = {ghi01.y, ghi01.w, ghi23.y, ghi23.w};
 #pragma unroll
@@ -487,7 +552,7 @@ __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const Bl
         }
     wait_vmcnt_chunks<LOADS, NBUF - 1>(n_issued - 1 - min(CPB - 1, total - 1));
     barrier_no_fence();
-    v4i X0[D], X1[D];      // packed operands of the current and the next K step
+    v4i X0[NB], X1[NB];    // packed operands of the current and the next K step
     read_step(ring + row_off, 0, X0);
 
     // one K step: unpack its operands and issue its MFMAs
@@ -496,16 +561,16 @@ __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const Bl
     // those MFMAs; the scheduling groups at the end keep MFMAs and VALU work
     // interleaved (one MFMA, then up to 6 VALU instructions).
     auto step = [&](const v4i *X) {
-        v4i A[D], B[D], R[D];
-        static_for<0, D>([&](auto kc) {
+        v4i A[NB], B[NB], R[NB];
+        static_for<0, NB>([&](auto kc) {
             constexpr int k = kc;
-            static_for<0, D>([&](auto bc) {
+            static_for<0, NB>([&](auto bc) {
                 constexpr int b = bc;
-                if constexpr (g3_block_pos<D>(SLOT, b) == k) {
+                if constexpr (g3_block_pos<D, RECT>(SLOT, b) == k) {
                     A[b] = X[b] ^ 0x08080808;
                     B[b] = X[b] ^ 0x07070707;
                     R[b] = X[b] & (int)0xF0F0F0F0;
-                    if constexpr (g3_owns_sums<D>(SLOT, b)) {
+                    if constexpr (g3_owns_sums<D, RECT>(SLOT, b)) {
 #pragma unroll
                         for (int k = 0; k < 4; ++k) {
                             int &z = k & 1 ? sz2[b] : sz[b];
@@ -518,16 +583,17 @@ __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const Bl
             });
             static_for<0, NTT>([&](auto tc) {
                 constexpr int t = tc;
-                if constexpr (g3_has<D>(SLOT, t) && g3_tile_pos<D>(SLOT, t) == k) {
-                    constexpr int q = g3_rank<D>(SLOT, t);
-                    acc_ab[q] = mfma_i8(A[tri_I(t)], B[tri_J(t)], acc_ab[q]);
-                    if constexpr (!g3_diag(t))
-                        acc_ba[q] = mfma_i8(B[tri_I(t)], A[tri_J(t)], acc_ba[q]);
-                    acc_rr[q] = mfma_i8(R[tri_I(t)], R[tri_J(t)], acc_rr[q]);
+                if constexpr (g3_has<D, RECT>(SLOT, t) && g3_tile_pos<D, RECT>(SLOT, t) == k) {
+                    constexpr int q = g3_rank<D, RECT>(SLOT, t);
+                    constexpr int I = g3_row<RECT>(D, t), J = g3_col<RECT>(D, t);
+                    acc_ab[q] = mfma_i8(A[I], B[J], acc_ab[q]);
+                    if constexpr (!g3_isdiag<RECT>(D, t))
+                        acc_ba[q] = mfma_i8(B[I], A[J], acc_ba[q]);
+                    acc_rr[q] = mfma_i8(R[I], R[J], acc_rr[q]);
                 }
             });
         });
-        static_for<0, g3_mfmas_of<D>(SLOT)>([&](auto) {
+        static_for<0, g3_mfmas_of<D, RECT>(SLOT)>([&](auto) {
             __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
             __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);   // up to six VALU
         });
@@ -588,14 +654,14 @@ __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const Bl
     }
 }
 
-template <int D, int ACC, int MB>
+template <int D, bool RECT, int ACC, int MB>
 __device__ __forceinline__ void g3_dispatch(uint8_t *smem, const G3Args &a, const BlockTable *bt)
 {
     switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {
-#define XC_CASE(W)                                        \
-    case W:                                               \
-        if constexpr (W < kG3Waves)                       \
-            g3_wave<D, W, ACC, MB>(smem, a, bt, a.volts); \
+#define XC_CASE(W)                                              \
+    case W:                                                     \
+        if constexpr (W < kG3Waves)                             \
+            g3_wave<D, RECT, W, ACC, MB>(smem, a, bt, a.volts); \
         break;
         XC_CASE(0) XC_CASE(1) XC_CASE(2) XC_CASE(3) XC_CASE(4) XC_CASE(5) XC_CASE(6) XC_CASE(7)
         XC_CASE(8) XC_CASE(9) XC_CASE(10) XC_CASE(11) XC_CASE(12) XC_CASE(13) XC_CASE(14) XC_CASE(15)

@@ -1,19 +1,21 @@
 // 4+4-bit int8-MFMA kernels of the X-engine, three-product variant (see
 // xc_gauss4.h): one persistent work-group per CU (two for D <= 3) walks its
-// channels as one continuous stream of LDS-DMA chunks; every region is the
-// whole triangle of a channel (N <= 192).
+// (channel, region) items as one continuous stream of LDS-DMA chunks.  A
+// channel of up to 6 blocks is one triangle; more blocks (D <= 4) split into
+// triangles of D blocks on the diagonal and D x D rectangles between them,
+// run as two launches (all triangles, then all rectangles).
 #include "xc_gauss4.h"
 
 namespace xc {
 namespace {
 
-template <int D, int ACC, int MB>
+template <int D, bool RECT, int ACC, int MB>
 __global__ __launch_bounds__(kG3Threads)
-__attribute__((amdgpu_waves_per_eu(g3_waves_per_eu(D), g3_waves_per_eu(D))))
+__attribute__((amdgpu_waves_per_eu(g3_waves_per_eu<RECT>(D), g3_waves_per_eu<RECT>(D))))
 void xc_gauss4_kernel(const G3Args a, const BlockTable bt)
 {
-    __shared__ __attribute__((aligned(1024))) uint8_t smem[g3_smem_bytes(D)];
-    g3_dispatch<D, ACC, MB>(smem, a, &bt);
+    __shared__ __attribute__((aligned(1024))) uint8_t smem[g3_smem_bytes<RECT>(D)];
+    g3_dispatch<D, RECT, ACC, MB>(smem, a, &bt);
 }
 
 // compute units of the current device (queried once per device)
@@ -32,32 +34,50 @@ int device_cu_count()
     return cached[dev];
 }
 
-template <int D>
-hipError_t launch_t(const G3Args &a, const BlockTable *bt, int accumulate, hipStream_t s)
+template <int D, bool RECT>
+hipError_t launch_shape(const G3Args &a, const BlockTable *bt, int accumulate, hipStream_t s)
 {
-    const int per = (a.F + 7) / 8;
-    const int m_max = device_cu_count() * g3_wgs_per_cu(D) / 8;
+    const int64_t items = (int64_t)a.F * a.nreg;
+    const int per = (int)((items + 7) / 8);
+    const int m_max = device_cu_count() * g3_wgs_per_cu<RECT>(D) / 8;
     const int grid = 8 * std::max(1, std::min(m_max, per));
     G3Args args = a;
     args.per = per;
     BlockTable table{};
     if (bt)
         table = *bt;
-    auto kern = bt ? (accumulate ? xc_gauss4_kernel<D, 1, 1> : xc_gauss4_kernel<D, 0, 1>)
-                   : (accumulate ? xc_gauss4_kernel<D, 1, 0> : xc_gauss4_kernel<D, 0, 0>);
+    auto kern = bt ? (accumulate ? xc_gauss4_kernel<D, RECT, 1, 1> : xc_gauss4_kernel<D, RECT, 0, 1>)
+                   : (accumulate ? xc_gauss4_kernel<D, RECT, 1, 0> : xc_gauss4_kernel<D, RECT, 0, 0>);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kG3Threads), 0, s, args, table);
     return hipGetLastError();
 }
 
-hipError_t launch_any(int D, const G3Args &a, const BlockTable *bt, int accumulate, hipStream_t s)
+// the triangles of every channel, then (several segments) the rectangles
+template <int D>
+hipError_t launch_t(const G3Args &a, int nseg, const BlockTable *bt, int accumulate, hipStream_t s)
+{
+    G3Args t = a;
+    t.nreg = nseg;
+    hipError_t e = launch_shape<D, false>(t, bt, accumulate, s);
+    if constexpr (D <= 4) {
+        if (e == hipSuccess && nseg > 1) {
+            G3Args r = a;
+            r.nreg = nseg * (nseg - 1) / 2;
+            e = launch_shape<D, true>(r, bt, accumulate, s);
+        }
+    }
+    return e;
+}
+
+hipError_t launch_any(int D, int nseg, const G3Args &a, const BlockTable *bt, int accumulate, hipStream_t s)
 {
     switch (D) {
-    case 1: return launch_t<1>(a, bt, accumulate, s);
-    case 2: return launch_t<2>(a, bt, accumulate, s);
-    case 3: return launch_t<3>(a, bt, accumulate, s);
-    case 4: return launch_t<4>(a, bt, accumulate, s);
-    case 5: return launch_t<5>(a, bt, accumulate, s);
-    case 6: return launch_t<6>(a, bt, accumulate, s);
+    case 1: return launch_t<1>(a, nseg, bt, accumulate, s);
+    case 2: return launch_t<2>(a, nseg, bt, accumulate, s);
+    case 3: return launch_t<3>(a, nseg, bt, accumulate, s);
+    case 4: return launch_t<4>(a, nseg, bt, accumulate, s);
+    case 5: return launch_t<5>(a, nseg, bt, accumulate, s);
+    case 6: return launch_t<6>(a, nseg, bt, accumulate, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -66,8 +86,10 @@ hipError_t launch_any(int D, const G3Args &a, const BlockTable *bt, int accumula
 
 bool gauss4_supported(const Plan &pl, int F, int N)
 {
-    return pl.nseg == 1 && pl.regions == 1 && pl.D >= 1 && pl.D <= 6 && N <= 32 * pl.D && N % 16 == 0 &&
-           F >= 1 && 64LL * F * N < (1LL << 31) - 16;
+    const bool shape = pl.nseg == 1 ? (pl.D >= 1 && pl.D <= 6 && N <= 32 * pl.D)
+                                    : (pl.D >= 1 && pl.D <= 4 && pl.nseg * pl.D * 32 >= N);
+    return shape && N % 16 == 0 && F >= 1 && 64LL * F * N < (1LL << 31) - 16 &&
+           (int64_t)F * pl.regions < (1LL << 30);
 }
 
 hipError_t launch_gauss4(const Plan &pl, const uint8_t *volts, int64_t T, int F, int N, int2 *acc, int accumulate,
@@ -83,7 +105,7 @@ hipError_t launch_gauss4(const Plan &pl, const uint8_t *volts, int64_t T, int F,
     a.N = N;
     a.out = acc;
     a.in = acc_in ? acc_in : acc;
-    return launch_any(pl.D, a, nullptr, accumulate, s);
+    return launch_any(pl.D, pl.nseg, a, nullptr, accumulate, s);
 }
 
 hipError_t launch_gauss4_blocks(const Plan &pl, const BlockTable &bt, int n_blocks, int F, int N, int2 *acc,
@@ -102,7 +124,7 @@ hipError_t launch_gauss4_blocks(const Plan &pl, const BlockTable &bt, int n_bloc
     a.N = N;
     a.out = acc;
     a.in = acc_in ? acc_in : acc;
-    return launch_any(pl.D, a, &bt, accumulate, s);
+    return launch_any(pl.D, pl.nseg, a, &bt, accumulate, s);
 }
 
 }  // namespace xc

@@ -148,6 +148,29 @@ def cmd_traffic(a):
     print(json.dumps(res, indent=1))
 
 
+def cmd_traffic_table(a):
+    """Per kernel instance: dispatches, mean HBM bytes fetched and written per
+    dispatch, the counters scaled by factors measured on a copy kernel of
+    one known size (a run where every dispatch of it has the same size)."""
+    fetch, write = _pmc(a.fetch, "FETCH_SIZE"), _pmc(a.write, "WRITE_SIZE")
+    f_scale, w_scale = a.fetch_scale, a.write_scale
+    lines = [f"rocprofv3 FETCH_SIZE / WRITE_SIZE per dispatch: {a.title}"]
+    lines += [f"command: {c}" for c in a.command]
+    lines.append(f"scale: FETCH_SIZE x {f_scale:.4f}, WRITE_SIZE x {w_scale:.4f}")
+    lines.append("")
+    lines.append(f"{'kernel':40s} {'dispatches':>10s} {'fetch_MB':>10s} {'write_MB':>10s}")
+    for k in sorted(set(fetch) | set(write)):
+        if not k.startswith("xc_"):
+            continue
+        nf = len(fetch.get(k, []))
+        fb = statistics.mean(fetch[k]) * 1024 * f_scale / 1e6 if k in fetch else float("nan")
+        wb = statistics.mean(write[k]) * 1024 * w_scale / 1e6 if k in write else float("nan")
+        lines.append(f"{k:40s} {nf:10d} {fb:10.1f} {wb:10.1f}")
+    for n in a.note or []:
+        lines.append(n)
+    print("\n".join(lines))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -164,6 +187,14 @@ def main(argv=None):
     f.add_argument("--write", required=True)
     f.add_argument("--counters")
     f.add_argument("--kernel", required=True)
+    tt = sub.add_parser("traffic-table")
+    tt.add_argument("--fetch", required=True)
+    tt.add_argument("--write", required=True)
+    tt.add_argument("--fetch-scale", type=float, required=True)
+    tt.add_argument("--write-scale", type=float, required=True)
+    tt.add_argument("--title", required=True)
+    tt.add_argument("--command", action="append", required=True)
+    tt.add_argument("--note", action="append")
     f.add_argument("--calib-kernel", default="xc_dump_kernel")
     f.add_argument("--calib-read", type=float, required=True)
     f.add_argument("--calib-write", type=float, required=True)
@@ -172,7 +203,7 @@ def main(argv=None):
     f.add_argument("--title", required=True)
     f.add_argument("--command", action="append", required=True)
     a = ap.parse_args(argv)
-    (cmd_trace if a.cmd == "trace" else cmd_traffic)(a)
+    {"trace": cmd_trace, "traffic": cmd_traffic, "traffic-table": cmd_traffic_table}[a.cmd](a)
 
 
 if __name__ == "__main__":

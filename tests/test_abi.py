@@ -171,7 +171,9 @@ def test_tuner_times_the_kernel_the_context_runs(monkeypatch):
     # one whole-triangle region per channel (tile 6): the three-product kernel;
     # a tile with rectangles between segments: the fused-product kernel
     assert X.xcorr_autotune_kernel(c4) == "xc_gauss4_kernel"
-    assert X.xcorr_autotune_kernel(X.make_config(192, 1024, 4, X.PATH_I8_MFMA, tile=4)) == "xc_mfma4f_kernel"
+    # several segments (triangles and rectangles) also run the three-product kernel
+    assert X.xcorr_autotune_kernel(X.make_config(192, 1024, 4, X.PATH_I8_MFMA, tile=4)) == "xc_gauss4_kernel"
+    assert X.xcorr_autotune_kernel(X.make_config(512, 64, 4, X.PATH_I8_MFMA, tile=4)) == "xc_gauss4_kernel"
     assert X.xcorr_autotune_kernel(X.make_config(100, 64, 4, X.PATH_I8_MFMA)) == "xc_mfma4f_kernel"   # N % 16
     monkeypatch.setenv("XCORR_MFMA4_VARIANT", "fused")
     assert X.xcorr_autotune_kernel(c4) == "xc_mfma4f_kernel"
@@ -192,10 +194,11 @@ def test_tune_cache_lines_are_used_only_for_their_kernel(tmp_path, monkeypatch):
     cache = tmp_path / "tune.txt"
     cache.write_text("4 192 1024 1 3\n"                          # old format: ignored
                      "4 192 1024 1 2 xc_mfma4_kernel\n"           # per-role kernel: not run
-                     "4 192 1024 1 4 xc_mfma4f_kernel\n"
-                     "4 192 1024 1 6 xc_mfma4f_kernel\n"          # tile 6 runs the three-product kernel
-                     "4 192 1024 1 5 xc_gauss4_kernel\n"          # tile 5 leaves rectangles: ignored
-                     "4 192 512 1 3 xc_mfma4f_kernel\n"           # another config
+                     "4 192 1024 1 4 xc_gauss4_kernel\n"
+                     "4 192 1024 1 4 xc_mfma4f_kernel\n"          # tile 4 runs the three-product kernel
+                     "4 192 1024 1 6 xc_mfma4f_kernel\n"          # so does tile 6
+                     "4 192 1024 1 5 xc_gauss4_kernel\n"          # tile 5 leaves 5 x 5 rectangles: no kernel
+                     "4 192 512 1 3 xc_gauss4_kernel\n"           # another config
                      "4 192 1024 1 3 xc_batch4_kernel\n"
                      "4 192 1024 1 5 xc_batch4_kernel\n")          # 5 is not a batch tile: ignored
     monkeypatch.setenv("XCORR_TUNE_CACHE", str(cache))

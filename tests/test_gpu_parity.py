@@ -65,7 +65,10 @@ def test_ragged_shapes_bit_exact(path, N, F, T):
 
 
 TILES = [(192, 2), (192, 3), (192, 4), (192, 6), (160, 5), (96, 3), (64, 2), (256, 4), (256, 2),
-         (130, 2), (300, 3), (512, 4), (20, 1)]
+         (130, 2), (300, 3), (512, 4), (20, 1),
+         # several segments whose last one runs past N (three-product rectangles
+         # with partial or empty blocks)
+         (208, 4), (400, 3), (336, 2), (272, 4), (112, 2)]
 
 
 # the default 4+4-bit kernel (fused products) and the per-role one
