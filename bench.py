@@ -188,7 +188,8 @@ def bench_precision8(dev, stream, reps: int) -> dict:
 
 def bench_batched(dev, stream, reps: int) -> dict:
     """Four arrays (64x256, 192x1024, 256x512, 512x128 inputs x channels,
-    2048 samples) in one persistent launch vs one launch per array."""
+    2048 samples) in one launch, the same launch replayed from a HIP graph,
+    and one launch per array and region shape."""
     import torch
 
     from paper_2406_19013_amd import synth
@@ -213,26 +214,33 @@ def bench_batched(dev, stream, reps: int) -> dict:
         for c, o in zip(cors, outs):
             c.dump(o, stream=stream)
 
-    batch_ms, _ = _timed(lambda: b.ingest(vs, stream=stream), stream, reps, after=dumps)
-
     def singles():
         for c, v in zip(cors, vs):
             c.ingest(v, T, stream=stream)
 
-    single_ms, _ = _timed(singles, stream, reps, after=dumps)
-    stream.synchronize()
     # the batched launch captured once in a graph and replayed
     g = torch.cuda.CUDAGraph()
     with torch.cuda.stream(stream):
         with torch.cuda.graph(g, stream=stream):
             b.ingest(vs, stream=stream)
     stream.synchronize()
+
     def replay():
         with torch.cuda.stream(stream):
             g.replay()
 
-    graph_ms, _ = _timed(replay, stream, reps, after=dumps)
+    # the three ways take turns over several rounds (the part's clock drifts
+    # as it warms, which would favour whichever ran first); medians per launch
+    import numpy as np
+    ways = {"batch": lambda: b.ingest(vs, stream=stream), "separate": singles, "graph": replay}
+    samples = {k: [] for k in ways}
+    rounds = 5
+    for _ in range(rounds):
+        for k, fn in ways.items():
+            _, ms = _timed(fn, stream, max(2, reps // rounds), after=dumps)
+            samples[k].extend(ms.tolist())
     stream.synchronize()
+    batch_ms, single_ms, graph_ms = (float(np.median(samples[k])) for k in ("batch", "separate", "graph"))
     if prev_cache is None:
         os.environ.pop("XCORR_TUNE_CACHE", None)
     else:

@@ -31,7 +31,8 @@ UNITS = [("xcorr_kernels.hip", [], "xcorr_kernels.o"), ("xcorr_api.cpp", [], "xc
          ("xcorr_pipe.cpp", [], "xcorr_pipe.o"), ("xcorr_reorder.cpp", [], "xcorr_reorder.o"), ("xcorr_cns.cpp", [], "xcorr_cns.o"),
          ("xcorr_mfma4.hip", [], "xcorr_mfma4.o"), ("xcorr_mfma4f.hip", [], "xcorr_mfma4f.o"),
          ("xcorr_batch.hip", [], "xcorr_batch.o"),
-         ("xcorr_gauss4.hip", [], "xcorr_gauss4.o"), ("xcorr_static.hip", [], "xcorr_static.o"),
+         ("xcorr_gauss4.hip", [], "xcorr_gauss4.o"), ("xcorr_gauss4_batch.hip", [], "xcorr_gauss4_batch.o"),
+         ("xcorr_static.hip", [], "xcorr_static.o"),
          ("xcorr_ceiling.hip", [], "xcorr_ceiling.o"),
          ("xcorr_fengine.hip", [], "xcorr_fengine.o"),
          ("xcorr_stokes.hip", [], "xcorr_stokes.o")] + [

@@ -291,6 +291,7 @@ struct G3Args {
     int per;                // items (channel, region) per XCD range
     int2 *out;              // [F][P] results
     const int2 *in;         // [F][P] running sums (ACC = 1)
+    int mrow0, mrows;       // work-group rows (blockIdx / 8) that serve these items
 };
 
 // First global block of a region's rows and of its columns: triangle r of a
@@ -314,7 +315,8 @@ __device__ __forceinline__ void g3_region_origin(int r, int &rb, int &cb)
 
 // One wave's share of a launch: its tiles of every channel item of its
 // work-group, K loop over the continuous chunk stream, and the epilogue of
-// each item.
+// each item.  ACC: 0 stores the sums of this launch, 1 adds the running sums
+// of `in`.
 template <int D, bool RECT, int SLOT, int ACC, int MB>
 __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const BlockTable *bt,
                                         const uint8_t *__restrict__ volts)
@@ -344,7 +346,7 @@ __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const Bl
 
     // this work-group's items (channel, region): the local items m, m + M, ...
     // of its XCD's range of consecutive items
-    const int xcd = blockIdx.x & 7, m = blockIdx.x >> 3, M = gridDim.x >> 3;
+    const int xcd = blockIdx.x & 7, m = (int)(blockIdx.x >> 3) - a.mrow0, M = a.mrows;
     const int r0 = xcd * a.per;
     const int rlen = min(a.per, a.F * a.nreg - r0);
     const int n_my = rlen > m ? (rlen - m + M - 1) / M : 0;

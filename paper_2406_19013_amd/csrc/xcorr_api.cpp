@@ -110,7 +110,10 @@ const char *kernel_for(const xcorr_config &c, int tile, bool batch)
     if (c.path == XCORR_PATH_PLAIN)
         return "xc_plain_kernel";
     if (batch)
-        return "xc_batch4_kernel";
+        return kernel4_from_env() == Kernel4::Gauss &&
+                       xc::gauss4_batch_shape(xc::make_plan(c.n_inputs, tile), c.n_chans, c.n_inputs)
+                   ? "xc_gauss4_batch_kernel"
+                   : "xc_batch4_kernel";
     if (c.sample_bits == 8)
         return c.path == XCORR_PATH_F16_MFMA ? "xc_mfma8_kernel_f16" : "xc_mfma8_kernel_i8";
     const Kernel4 k = kernel4_from_env();
@@ -333,7 +336,7 @@ struct xcorr_batch {
     std::vector<xcorr_ctx *> ctx;
     std::vector<xc::Plan> plan;
     int *queue;
-    int grid;
+    int grid;   // work-groups of the queue-driven kernel: one per CU
 };
 
 extern "C" {
@@ -669,7 +672,13 @@ int xcorr_batch_ingest(xcorr_batch *b, const void *const *d_volts, const int64_t
         if (items > (1LL << 30))
             return set_error(XCORR_E_INVAL, "too many work items in one batch");
         args.total = (int)items;
-        const hipError_t e = xc::launch_batch4(args, b->queue, vec, std::min<int64_t>(b->grid, items), s);
+        // the three-product kernel when it carries every member, else the
+        // queue-driven four-product kernel
+        bool gauss = kernel4_from_env() == Kernel4::Gauss;
+        for (int a = 0; a < args.n && gauss; ++a)
+            gauss = xc::gauss4_batch_supported(args.a[a]);
+        const hipError_t e = gauss ? xc::launch_gauss4_batch(args, b->grid, s)
+                                   : xc::launch_batch4(args, b->queue, vec, std::min<int64_t>(b->grid, items), s);
         if (e != hipSuccess)
             return hip_fail(e, "batch launch");
         for (int a = 0; a < n; ++a)
@@ -878,6 +887,8 @@ static int autotune_impl(const xcorr_config *cfg, void *d_scratch, size_t scratc
                 if (items > (1LL << 30))
                     return hipErrorInvalidValue;
                 args.total = (int)items;
+                if (k4 == Kernel4::Gauss && xc::gauss4_batch_supported(A))
+                    return xc::launch_gauss4_batch(args, cus, s);
                 const int vec = c.n_inputs % 16 == 0 && 64LL * c.n_chans * c.n_inputs < (1LL << 31) - 16;
                 return xc::launch_batch4(args, queue, vec, (int)std::min<int64_t>(cus, items), s);
             }

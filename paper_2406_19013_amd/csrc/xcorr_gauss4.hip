@@ -43,6 +43,8 @@ hipError_t launch_shape(const G3Args &a, const BlockTable *bt, int accumulate, h
     const int grid = 8 * std::max(1, std::min(m_max, per));
     G3Args args = a;
     args.per = per;
+    args.mrow0 = 0;
+    args.mrows = grid / 8;
     BlockTable table{};
     if (bt)
         table = *bt;

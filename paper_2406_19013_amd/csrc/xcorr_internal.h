@@ -124,6 +124,13 @@ struct BatchArgs {
 // every launch leaves it zero again.  vec: every array has N % 16 == 0, a
 // 16-byte aligned input and 64 * F * N < 2^31 - 16.
 hipError_t launch_batch4(const BatchArgs &args, int *queue, int vec, int grid, hipStream_t s);
+// The batch on the three-product kernel: every array must pass
+// gauss4_batch_supported (a plan of 2, 3, 4 or 6 blocks that
+// gauss4_batch_shape accepts, a 16-byte-aligned input); needs no queue.
+// cus: compute units of the device.
+bool gauss4_batch_shape(const Plan &pl, int F, int N);
+bool gauss4_batch_supported(const BatchArray &A);
+hipError_t launch_gauss4_batch(const BatchArgs &args, int cus, hipStream_t s);
 hipError_t launch_fill_zero(int *p, int n, hipStream_t s);
 hipError_t launch_fill_pattern(uint8_t *p, int64_t n, int eight_bit, hipStream_t s);
 

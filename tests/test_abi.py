@@ -175,6 +175,11 @@ def test_tuner_times_the_kernel_the_context_runs(monkeypatch):
     assert X.xcorr_autotune_kernel(X.make_config(192, 1024, 4, X.PATH_I8_MFMA, tile=4)) == "xc_gauss4_kernel"
     assert X.xcorr_autotune_kernel(X.make_config(512, 64, 4, X.PATH_I8_MFMA, tile=4)) == "xc_gauss4_kernel"
     assert X.xcorr_autotune_kernel(X.make_config(100, 64, 4, X.PATH_I8_MFMA)) == "xc_mfma4f_kernel"   # N % 16
+    # the batched launch: the three-product batch kernel where it carries the
+    # plan, else the queue-driven four-product one
+    assert X.xcorr_autotune_kernel(c4, batch=True) == "xc_gauss4_batch_kernel"
+    assert X.xcorr_autotune_kernel(X.make_config(512, 64, 4, X.PATH_I8_MFMA), batch=True) == "xc_gauss4_batch_kernel"
+    assert X.xcorr_autotune_kernel(X.make_config(100, 64, 4, X.PATH_I8_MFMA), batch=True) == "xc_batch4_kernel"
     monkeypatch.setenv("XCORR_MFMA4_VARIANT", "fused")
     assert X.xcorr_autotune_kernel(c4) == "xc_mfma4f_kernel"
     assert X.xcorr_autotune_kernel(c4, batch=True) == "xc_batch4_kernel"
@@ -199,8 +204,9 @@ def test_tune_cache_lines_are_used_only_for_their_kernel(tmp_path, monkeypatch):
                      "4 192 1024 1 6 xc_mfma4f_kernel\n"          # so does tile 6
                      "4 192 1024 1 5 xc_gauss4_kernel\n"          # tile 5 leaves 5 x 5 rectangles: no kernel
                      "4 192 512 1 3 xc_gauss4_kernel\n"           # another config
-                     "4 192 1024 1 3 xc_batch4_kernel\n"
-                     "4 192 1024 1 5 xc_batch4_kernel\n")          # 5 is not a batch tile: ignored
+                     "4 192 1024 1 3 xc_gauss4_batch_kernel\n"
+                     "4 192 1024 1 2 xc_batch4_kernel\n"           # the batch runs the three-product kernel
+                     "4 192 1024 1 5 xc_gauss4_batch_kernel\n")    # 5 is not a batch tile: ignored
     monkeypatch.setenv("XCORR_TUNE_CACHE", str(cache))
     cfg = X.make_config(192, 1024, 4, X.PATH_I8_MFMA)
     assert X.xcorr_plan_tile(cfg) == (4, True)

@@ -29,8 +29,9 @@ def dump_all(cors):
     return [(o.cpu().numpy(), n) for o, n in outs]
 
 
-# (N, F, T): uneven inputs, channels and sample counts; all N % 16 == 0 takes
-# the LDS-DMA kernel, any other N the register-staged one
+# (N, F, T): uneven inputs, channels and sample counts; a batch whose every
+# N % 16 == 0 runs the three-product batch kernel (triangles of 2, 4 and 6
+# blocks, rectangles of 4 here), any other N the queue-driven one
 VEC_SET = [(64, 6, 300), (192, 3, 1000), (256, 2, 77), (32, 5, 2048), (512, 1, 130)]
 RAGGED_SET = [(100, 3, 77), (20, 4, 515), (192, 2, 64), (33, 3, 200)]
 
@@ -49,10 +50,12 @@ def test_batch_matches_oracle(arrays):
     b.close()
 
 
-def test_batch_uneven_ingests_accumulate_and_skip():
+@pytest.mark.parametrize("arrays", [[(64, 3), (96, 2), (20, 4)], [(64, 3), (96, 2), (160, 4)]],
+                         ids=["queue", "three_product"])
+def test_batch_uneven_ingests_accumulate_and_skip(arrays):
     """Three batched ingests with per-array counts (some 0) add up to the
     oracle over each array's concatenated samples."""
-    arrays = [(64, 3), (96, 2), (20, 4)]
+    _say(f"uneven ingests {arrays}")
     counts = [[100, 0, 33], [1, 50, 0], [129, 7, 64]]
     cors = [X.Correlator(N, F, 4, X.PATH_I8_MFMA) for N, F in arrays]
     b = X.Batch(cors)
@@ -71,6 +74,31 @@ def test_batch_uneven_ingests_accumulate_and_skip():
         v = torch.cat(p)
         assert n == v.shape[0]
         assert np.array_equal(got, want(v, N, F))
+    b.close()
+
+
+def test_batch_every_region_shape(tmp_path, monkeypatch):
+    """Tiles from the batch tune cache put every shape the three-product batch
+    kernel carries into one launch: triangles of 2, 3, 4 and 6 blocks and
+    rectangles of 2, 3 and 4 (several segments, the last one partial)."""
+    cache = tmp_path / "tune.txt"
+    cache.write_text("4 320 2 1 2 xc_gauss4_batch_kernel\n"
+                     "4 288 3 1 3 xc_gauss4_batch_kernel\n"
+                     "4 208 2 1 4 xc_gauss4_batch_kernel\n"
+                     "4 128 2 1 4 xc_gauss4_batch_kernel\n")
+    monkeypatch.setenv("XCORR_TUNE_CACHE", str(cache))
+    arrays = [(320, 2, 150), (288, 3, 100), (208, 2, 90), (128, 2, 70), (96, 2, 64), (160, 1, 33), (48, 3, 129)]
+    _say(f"batch region shapes {arrays}")
+    assert [X.xcorr_autotune_kernel(X.make_config(N, F, 4, X.PATH_I8_MFMA), batch=True)
+            for N, F, _ in arrays] == ["xc_gauss4_batch_kernel"] * len(arrays)
+    vs = [synth.uniform_volts4(N, F, T, seed=(3008, N, F, T)) for N, F, T in arrays]
+    cors = [X.Correlator(N, F, 4, X.PATH_I8_MFMA) for N, F, _ in arrays]
+    b = X.Batch(cors)
+    assert b.tiles == [2, 3, 4, 4, 3, 6, 2], b.tiles
+    b.ingest([v.cuda() for v in vs])
+    for (got, n), v, (N, F, T) in zip(dump_all(cors), vs, arrays):
+        assert n == T
+        assert np.array_equal(got, want(v, N, F)), (N, F, T)
     b.close()
 
 
@@ -130,11 +158,14 @@ def test_batched_workload_matches_single_path():
     b.close()
 
 
-def test_batch_graph_replay():
+@pytest.mark.parametrize("arrays", [[(64, 4, 512), (192, 2, 256), (100, 3, 96)],
+                                    [(64, 4, 512), (192, 2, 256), (320, 3, 96)]],
+                         ids=["queue", "three_product"])
+def test_batch_graph_replay(arrays):
     """Capture [batched ingest, per-array dumps] in a HIP graph; between
     replays refill the inputs and run eager work on the same arrays; every
     replay must equal the oracle for the inputs it saw."""
-    arrays = [(64, 4, 512), (192, 2, 256), (100, 3, 96)]
+    _say(f"batch graph {arrays}")
     cors = [X.Correlator(N, F, 4, X.PATH_I8_MFMA) for N, F, _ in arrays]
     b = X.Batch(cors)
     vin = [torch.empty((T, F, N), dtype=torch.uint8, device="cuda") for N, F, T in arrays]
@@ -207,16 +238,17 @@ def test_autotune_picks_supported_tile_and_caches(tmp_path, monkeypatch, bits, p
 
 
 def test_batch_autotune_times_the_batched_kernel_and_batch_uses_it(tmp_path, monkeypatch):
-    """The batch tuner times the persistent kernel over the tiles it carries
-    and writes an xc_batch4_kernel line; a batch built afterwards takes that
-    tile for the member (the member's own single-array tile is separate) and
-    stays exact."""
+    """The batch tuner times the batched kernel over the tiles it carries
+    and writes a line naming it; a batch built afterwards takes that tile for
+    the member (the member's own single-array tile is separate) and stays
+    exact."""
     cache = tmp_path / "tune.txt"
     monkeypatch.setenv("XCORR_TUNE_CACHE", str(cache))
+    monkeypatch.delenv("XCORR_MFMA4_VARIANT", raising=False)
     N, F, T = 256, 32, 130
     best = X.autotune(N, F, 4, X.PATH_I8_MFMA, batch=True)
     assert best in (2, 3, 4)
-    assert cache.read_text().split() == ["4", str(N), str(F), "1", str(best), "xc_batch4_kernel"]
+    assert cache.read_text().split() == ["4", str(N), str(F), "1", str(best), "xc_gauss4_batch_kernel"]
     cfg = X.make_config(N, F, 4, X.PATH_I8_MFMA)
     assert X.xcorr_plan_tile(cfg, batch=True) == (best, True)
     assert X.xcorr_plan_tile(cfg) == (4, False)          # no line for the single-array kernel
