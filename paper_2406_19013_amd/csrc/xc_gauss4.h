@@ -409,7 +409,7 @@ __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const Bl
 #pragma unroll
         for (int k = 0; k < LOADS; ++k)
             __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (__attribute__((address_space(3))) void *)(dst + k * 1024),
-                                                     16, voff[k], 0, 0, kStreamLoadPolicy);
+                                                     16, voff[k], 0, 0, RECT ? kSharedLoadPolicy : kStreamLoadPolicy);
         if (++is_c == nch) {
             is_c = 0;
             if (++is_k < n_my)

@@ -130,6 +130,10 @@ constexpr int kBufferOutOfRange = (int)0xFFFFFFF0;  // any offset >= num_records
 // is read exactly once per launch, as a stream.  Measured 9 % faster on the
 // 192-input kernel than the default policy, with identical results.
 constexpr int kStreamLoadPolicy = 1 | 2 | 16;
+// Loads whose bytes other work-groups of the XCD read at about the same time
+// (a segment of inputs shared by the rectangles of one channel): the default
+// policy, which keeps them in L2.
+constexpr int kSharedLoadPolicy = 0;
 
 // Work-group barrier without the release/acquire fence of __syncthreads (the
 // fence would wait for every LDS-DMA load in flight, i.e. drain the ring).
