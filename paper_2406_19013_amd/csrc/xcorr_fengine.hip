@@ -3,18 +3,20 @@
 // 1024 channels -> per-(input, channel) EQ gain -> 4+4-bit requantisation ->
 // corner turn into the X-engine's [T][F][N] order.
 //
-// Persistent work-groups of 4 waves; an item is one spectrum m of 16 inputs,
-// 4 per wave, each filtered and transformed by one wave.  Per input and
-// spectrum:
+// Persistent work-groups of 8 waves (two per SIMD); an item is one spectrum
+// m of 16 inputs, 2 per wave, each filtered and transformed by one wave.  Per
+// input and spectrum:
 //   y[q] = sum_k h[k P + q] x[(m + k) P + q]            q < P = 2048
 //   z[n] = y[2n] + i y[2n + 1]                          n < 1024
 //   Z    = 1024-point complex DFT of z (radix 16 x 16 x 4)
 //   Y[c] = (Z[c] + Z*[N - c]) / 2 - i W^c (Z[c] - Z*[N - c]) / 2,  W = e^{-2 pi i / 2048}
 //   code = pack(clip(rint(g Re Y)), clip(rint(g Im Y)))  for channels c < 1024
 // A lane reads 32 consecutive samples of each tap with 16-byte loads (one
-// input ahead of the one it transforms) and keeps the 128 prototype
-// coefficients of its sample positions in registers for the work-group's
-// life; four LDS exchanges per transform (into the stride-64 order, between
+// input ahead of the one it transforms); the prototype is copied into LDS
+// once per work-group, ordered so that the 128 coefficients of a lane's sample
+// positions come as 32 conflict-free 16-byte reads per transform (held in
+// registers they took 512 per lane and left room for one wave per SIMD);
+// four LDS exchanges per transform (into the stride-64 order, between
 // the three radix passes, and for the Z[N - c] pairs).  Twiddles are built
 // per lane from one base value by short power products (at most three
 // roundings deep).  The 16 inputs' codes are gathered in LDS and leave as one
@@ -37,13 +39,14 @@ constexpr int kFeP = 2048;          // real points per spectrum
 constexpr int kFeN = kFeP / 2;      // complex FFT size and channel count
 constexpr int kFeTaps = 4;
 constexpr int kFeGroup = 16;        // inputs per item
-constexpr int kFeWaves = 4;
+constexpr int kFeWaves = 8;
 constexpr int kFeThreads = 64 * kFeWaves;
 constexpr int kFeInputsPerWave = kFeGroup / kFeWaves;
-constexpr int kFeWgsPerCu = 1;   // one wave per SIMD: 512 registers for coefficients, prefetch and FFT
+constexpr int kFeWgsPerCu = 1;   // 8 waves: two per SIMD, up to 256 registers each
 constexpr int kFeBufStride = 17;                    // float2 per row of the pass exchanges (16 + 1 pad)
 constexpr int kFeBufFloats = 2 * 64 * kFeBufStride;  // per wave: 64 rows
 constexpr int kFeCodeStride = 20;                   // bytes per channel row of the code tile (16 + pad)
+constexpr int kFeSmemProto = kFeTaps * kFeP * 4;    // the prototype, 32 KB
 
 // ---- twiddle tables, computed at compile time in double ----------------------
 
@@ -218,28 +221,55 @@ __device__ __forceinline__ float byte_at(const u32x4 &v, int t)
     return (float)(int8_t)(w >> (8 * (t & 3)));
 }
 
-// One wave's FFT of one (input, spectrum) from its raw samples: returns the
-// 16 channel values c = lane + 64 v (v < 16) of the real spectrum in y[v].
-// hc[k][t] = h[k P + 32 lane + t].
+// One wave's transform of one (input, spectrum), in two parts: the FIR of
+// its raw samples (after which the raw registers take the next input's
+// loads), then the FFT, which returns the 16 channel values c = lane + 64 v
+// (v < 16) of the real spectrum in y[v].
+// hl: the prototype in LDS, float4 (k, t4, lane) = h[k P + 32 lane + 4 t4 ..].
 struct FeBases {
     cf w1024, w64, w2048;   // W1024^lane, W64^(lane % 4), W2048^lane
 };
-__device__ __forceinline__ void fe_transform(const FeRaw &raw, const float (&hc)[kFeTaps][32], const FeBases &bs,
-                                             float *buf, cf (&y)[16])
+__device__ __forceinline__ void fe_fir(const FeRaw &raw, const float4 *hl, cf (&z)[16])
 {
     const int lane = threadIdx.x & 63;
-    // FIR on this lane's 32 samples -> z[n] for n = 16 lane + j
-    cf z[16];
+    // FIR on this lane's 32 samples -> z[n] for n = 16 lane + j; samples
+    // 4 t4 .. 4 t4 + 3 make z[2 t4] and z[2 t4 + 1]
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        float re = 0.f, im = 0.f;
+    for (int t4 = 0; t4 < 8; ++t4) {
+        // The coefficient reads are the same for every transform: left alone
+        // the compiler hoists or clusters all 32 (128 registers live at
+        // once).  An opaque offset behind a memory clobber keeps each group
+        // of four between its neighbours.
+        int l = lane;
+        asm volatile("" : "+v"(l) : : "memory");
+        float r0 = 0.f, i0 = 0.f, r1 = 0.f, i1 = 0.f;
 #pragma unroll
         for (int k = 0; k < kFeTaps; ++k) {
-            re = fmaf(hc[k][2 * j], byte_at(raw.v[k][j >> 3], (2 * j) & 15), re);
-            im = fmaf(hc[k][2 * j + 1], byte_at(raw.v[k][j >> 3], (2 * j + 1) & 15), im);
+            const float4 h = hl[(k * 8 + t4) * 64 + l];
+            const u32x4 &v = raw.v[k][t4 >> 2];
+            const int t = (4 * t4) & 15;
+            r0 = fmaf(h.x, byte_at(v, t), r0);
+            i0 = fmaf(h.y, byte_at(v, t + 1), i0);
+            r1 = fmaf(h.z, byte_at(v, t + 2), r1);
+            i1 = fmaf(h.w, byte_at(v, t + 3), i1);
         }
-        z[j] = cf{re, im};
+        z[2 * t4] = cf{r0, i0};
+        z[2 * t4 + 1] = cf{r1, i1};
     }
+}
+
+__device__ __forceinline__ void fe_fft(cf (&z)[16], const FeBases &bs, float *buf, cf (&y)[16])
+{
+    // the exchange addresses are the same for every transform; an opaque lane
+    // makes the compiler form them here instead of keeping about a hundred
+    // of them live across the loop (which spilled with two waves per SIMD)
+    int lane = threadIdx.x & 63;
+    asm volatile("" : "+v"(lane));
+    // likewise the twiddles derived from the per-lane bases (about a hundred
+    // registers if kept across the loop): formed anew for each transform
+    FeBases b = bs;
+    asm volatile("" : "+v"(b.w1024.r), "+v"(b.w1024.i), "+v"(b.w64.r), "+v"(b.w64.i), "+v"(b.w2048.r),
+                 "+v"(b.w2048.i));
     // exchange 0: z at n + n / 16, read back with stride 64 (n = 64 n1 + lane)
 #pragma unroll
     for (int j = 0; j < 16; ++j)
@@ -255,7 +285,7 @@ __device__ __forceinline__ void fe_transform(const FeRaw &raw, const float (&hc)
     dft16(z);
     {
         cf tw[16];
-        powers16(bs.w1024, tw);
+        powers16(b.w1024, tw);
 #pragma unroll
         for (int k1 = 0; k1 < 16; ++k1) {
             const cf v = cmul(z[k1], tw[k1]);
@@ -275,7 +305,7 @@ __device__ __forceinline__ void fe_transform(const FeRaw &raw, const float (&hc)
     dft16(z);
     {
         cf tw[16];
-        powers16(bs.w64, tw);
+        powers16(b.w64, tw);
 #pragma unroll
         for (int j1 = 0; j1 < 16; ++j1)
             z[j1] = cmul(z[j1], tw[j1]);
@@ -313,7 +343,7 @@ __device__ __forceinline__ void fe_transform(const FeRaw &raw, const float (&hc)
         }
     lds_sync();
     // real spectrum of channels c = lane + 64 v: W2048^c = W2048^lane W32^v
-    const cf wl = bs.w2048;
+    const cf wl = b.w2048;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
         const int c = lane + 64 * v;
@@ -345,20 +375,16 @@ __device__ __forceinline__ void fengine_body(uint8_t *smem, const FeArgs &a)
     if (first >= end)
         return;
 
-    float *buf = (float *)smem + w * kFeBufFloats;
-    uint8_t *codes = smem + kFeWaves * kFeBufFloats * sizeof(float);
+    float4 *hl = (float4 *)smem;
+    float *buf = (float *)(smem + kFeSmemProto) + w * kFeBufFloats;
+    uint8_t *codes = smem + kFeSmemProto + kFeWaves * kFeBufFloats * sizeof(float);
 
-    float hc[kFeTaps][32];
-#pragma unroll
-    for (int k = 0; k < kFeTaps; ++k)
-#pragma unroll
-        for (int t = 0; t < 32; t += 4) {
-            const float4 v = *(const float4 *)(a.h + k * kFeP + 32 * lane + t);
-            hc[k][t] = v.x;
-            hc[k][t + 1] = v.y;
-            hc[k][t + 2] = v.z;
-            hc[k][t + 3] = v.w;
-        }
+    // the prototype into LDS: float4 (k, t4, l) at (k * 8 + t4) * 64 + l
+    for (int idx = threadIdx.x; idx < kFeTaps * 8 * 64; idx += kFeThreads) {
+        const int k = idx >> 9, t4 = (idx >> 6) & 7, l = idx & 63;
+        hl[idx] = *(const float4 *)(a.h + k * kFeP + 32 * l + 4 * t4);
+    }
+    __syncthreads();
 
     const FeBases bases{cf{kW1024.re[lane], kW1024.im[lane]}, cf{kW64.re[lane & 3], kW64.im[lane & 3]},
                         cf{kW2048.re[lane], kW2048.im[lane]}};
@@ -372,7 +398,8 @@ __device__ __forceinline__ void fengine_body(uint8_t *smem, const FeArgs &a)
         const int g = (int)(it / a.n_spectra);
         for (int ii = 0; ii < kFeInputsPerWave; ++ii) {
             const int input = g * kFeGroup + w * kFeInputsPerWave + ii;
-            const FeRaw cur = raw;
+            cf z[16];
+            fe_fir(raw, hl, z);
             if (ii + 1 < kFeInputsPerWave)
                 fe_load(a, input + 1, m, raw);
             else if (it + stride < end)
@@ -387,7 +414,7 @@ __device__ __forceinline__ void fengine_body(uint8_t *smem, const FeArgs &a)
                     gv16[v] = gi[lane + 64 * v];
             }
             cf y[16];
-            fe_transform(cur, hc, bases, buf, y);
+            fe_fft(z, bases, buf, y);
             if constexpr (CODES) {
 #pragma unroll
                 for (int v = 0; v < 16; ++v) {
@@ -417,17 +444,17 @@ __device__ __forceinline__ void fengine_body(uint8_t *smem, const FeArgs &a)
     }
 }
 
-constexpr int kFeSmemCodes = kFeWaves * kFeBufFloats * 4 + kFeN * kFeCodeStride;
-constexpr int kFeSmemSpectra = kFeWaves * kFeBufFloats * 4;
+constexpr int kFeSmemCodes = kFeSmemProto + kFeWaves * kFeBufFloats * 4 + kFeN * kFeCodeStride;
+constexpr int kFeSmemSpectra = kFeSmemProto + kFeWaves * kFeBufFloats * 4;
 
-__global__ __launch_bounds__(kFeThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
+__global__ __launch_bounds__(kFeThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void xc_fengine_kernel(const FeArgs a)
 {
     __shared__ __attribute__((aligned(16))) uint8_t smem[kFeSmemCodes];
     fengine_body<true>(smem, a);
 }
 
-__global__ __launch_bounds__(kFeThreads) __attribute__((amdgpu_waves_per_eu(1, 1)))
+__global__ __launch_bounds__(kFeThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void xc_pfb_spectra_kernel(const FeArgs a)
 {
     __shared__ __attribute__((aligned(16))) uint8_t smem[kFeSmemSpectra];
