@@ -49,20 +49,30 @@ constexpr int g3_ntiles(int D) { return D * (D + 1) / 2; }
 constexpr bool g3_diag(int t) { return tri_I(t) == tri_J(t); }
 constexpr int g3_abs(int x) { return x < 0 ? -x : x; }
 
-// Region geometry.  A triangle of D blocks: local blocks 0 .. D-1, tiles
-// (I, J <= I) in row-major order.  A D x D rectangle below the diagonal
-// (D <= 4): local row blocks 0 .. D-1 and column blocks D .. 2D-1, tile t =
-// (t / D, D + t % D), no diagonal tiles.
-template <bool RECT>
-constexpr int g3_tiles(int D) { return RECT ? D * D : D * (D + 1) / 2; }
-template <bool RECT>
-constexpr int g3_blocks(int D) { return RECT ? 2 * D : D; }
-template <bool RECT>
-constexpr int g3_row(int D, int t) { return RECT ? t / D : tri_I(t); }
-template <bool RECT>
-constexpr int g3_col(int D, int t) { return RECT ? D + t % D : tri_J(t); }
-template <bool RECT>
-constexpr bool g3_isdiag(int D, int t) { return !RECT && tri_I(t) == tri_J(t); }
+// Region geometry, by shape SH.  A triangle (SH = 0) of D blocks: local
+// blocks 0 .. D-1, tiles (I, J <= I) in row-major order.  A D x D rectangle
+// below the diagonal (SH = 1, D <= 4): local row blocks 0 .. D-1 and column
+// blocks D .. 2D-1, tile t = (t / D, D + t % D), no diagonal tiles.  A
+// channel pair (SH = 2): the triangles of one segment in two neighbouring
+// channels, local blocks 0 .. D-1 of the first and D .. 2D-1 of the second,
+// the second triangle's tiles after the first's.
+constexpr int kTri = 0, kRect = 1, kPair = 2;
+template <int SH>
+constexpr int g3_tiles(int D) { return SH == kRect ? D * D : SH == kPair ? D * (D + 1) : D * (D + 1) / 2; }
+template <int SH>
+constexpr int g3_blocks(int D) { return SH == kTri ? D : 2 * D; }
+template <int SH>
+constexpr int g3_row(int D, int t)
+{
+    return SH == kRect ? t / D : SH == kPair && t >= D * (D + 1) / 2 ? D + tri_I(t - D * (D + 1) / 2) : tri_I(t);
+}
+template <int SH>
+constexpr int g3_col(int D, int t)
+{
+    return SH == kRect ? D + t % D : SH == kPair && t >= D * (D + 1) / 2 ? D + tri_J(t - D * (D + 1) / 2) : tri_J(t);
+}
+template <int SH>
+constexpr bool g3_isdiag(int D, int t) { return SH != kRect && g3_row<SH>(D, t) == g3_col<SH>(D, t); }
 
 // Waves per work-group: two per SIMD, 256 registers each.
 #ifndef XC_G3_WAVES
@@ -78,13 +88,13 @@ struct G3Split {
     uint32_t mask[kG3MaxWaves];
     int sum_owner[8];   // wave slot that sums the forms of local block b
 };
-template <bool RECT>
-constexpr int g3_units(int D, int t) { return g3_isdiag<RECT>(D, t) ? 2 : 3; }
-template <bool RECT>
+template <int SH>
+constexpr int g3_units(int D, int t) { return g3_isdiag<SH>(D, t) ? 2 : 3; }
+template <int SH>
 constexpr bool g3_touches(int D, uint32_t mask, int b)
 {
-    for (int t = 0; t < g3_tiles<RECT>(D); ++t)
-        if ((mask >> t & 1) && (g3_row<RECT>(D, t) == b || g3_col<RECT>(D, t) == b))
+    for (int t = 0; t < g3_tiles<SH>(D); ++t)
+        if ((mask >> t & 1) && (g3_row<SH>(D, t) == b || g3_col<SH>(D, t) == b))
             return true;
     return false;
 }
@@ -94,14 +104,14 @@ constexpr bool g3_touches(int D, uint32_t mask, int b)
 // per diagonal tile) is closest to k/W of the total; segments go to SIMDs
 // largest first, each to the SIMD with the least MFMA work so far; the sums
 // of a block go to the least-loaded wave that reads it.
-template <bool RECT>
+template <int SH>
 constexpr G3Split g3_contiguous_split(int D, int W)
 {
     G3Split sp{};
-    const int NT = g3_tiles<RECT>(D);
+    const int NT = g3_tiles<SH>(D);
     int cum[6 * 7 / 2 + 1] = {};
     for (int t = 0; t < NT; ++t)
-        cum[t + 1] = cum[t] + g3_units<RECT>(D, t);
+        cum[t + 1] = cum[t] + g3_units<SH>(D, t);
     const int U = cum[NT];
     int bound[kG3MaxWaves + 1] = {};
     for (int k = 1; k < W; ++k) {
@@ -134,10 +144,10 @@ constexpr G3Split g3_contiguous_split(int D, int W)
             sp.mask[slot] |= 1u << t;
         units[slot] = su[k];
     }
-    for (int b = 0; b < g3_blocks<RECT>(D); ++b) {
+    for (int b = 0; b < g3_blocks<SH>(D); ++b) {
         int best = -1;
         for (int s = 0; s < W; ++s)
-            if (g3_touches<RECT>(D, sp.mask[s], b) && (best < 0 || units[s] < units[best]))
+            if (g3_touches<SH>(D, sp.mask[s], b) && (best < 0 || units[s] < units[best]))
                 best = s;
         sp.sum_owner[b] = best;
         if (best >= 0)
@@ -155,63 +165,63 @@ constexpr G3Split g3_contiguous_split(int D, int W)
 //          6 {(5,1) (5,5)}  7 {(2,1) (3,2) (3,3)}
 //   D = 5: slot 0 {(4,2)}  1 {(4,3) (4,4)}  2 {(1,0) (1,1)}  3 {(0,0) (4,0)}
 //          4 {(3,0) (3,3)}  5 {(2,2) (3,2)}  6 {(2,0) (2,1)}  7 {(3,1) (4,1)}
-template <bool RECT>
+template <int SH>
 constexpr G3Split g3_make_split(int D, int W)
 {
-    if (!RECT && W == 8 && D == 6)
+    if (SH == kTri && W == 8 && D == 6)
         return G3Split{{0x804, 0x1020, 0xc2000, 0x4401, 0x28008, 0xc2, 0x110000, 0x310}, {3, 0, 1, 2, 0, 6, -1, -1}};
-    if (!RECT && W == 8 && D == 5)
+    if (SH == kTri && W == 8 && D == 5)
         return G3Split{{0x1000, 0x6000, 0x6, 0x401, 0x240, 0x120, 0x18, 0x880}, {4, 2, 5, 1, 0, -1, -1, -1}};
-    return g3_contiguous_split<RECT>(D, W);
+    return g3_contiguous_split<SH>(D, W);
 }
-template <int D, bool RECT>
-constexpr G3Split kG3Split = g3_make_split<RECT>(D, kG3Waves);
+template <int D, int SH>
+constexpr G3Split kG3Split = g3_make_split<SH>(D, kG3Waves);
 
-template <int D, bool RECT>
-constexpr uint32_t g3_mask(int s) { return kG3Split<D, RECT>.mask[s]; }
-template <int D, bool RECT>
-constexpr bool g3_has(int s, int t) { return t < 32 && (g3_mask<D, RECT>(s) >> t & 1); }
+template <int D, int SH>
+constexpr uint32_t g3_mask(int s) { return kG3Split<D, SH>.mask[s]; }
+template <int D, int SH>
+constexpr bool g3_has(int s, int t) { return t < 32 && (g3_mask<D, SH>(s) >> t & 1); }
 // position of tile t among the tiles of slot s (its accumulator index)
-template <int D, bool RECT>
+template <int D, int SH>
 constexpr int g3_rank(int s, int t)
 {
     int r = 0;
     for (int u = 0; u < t; ++u)
-        r += g3_has<D, RECT>(s, u);
+        r += g3_has<D, SH>(s, u);
     return r;
 }
-template <int D, bool RECT>
-constexpr int g3_ntiles_of(int s) { return g3_rank<D, RECT>(s, g3_tiles<RECT>(D)); }
-template <int D, bool RECT>
-constexpr bool g3_uses_block(int s, int b) { return g3_touches<RECT>(D, g3_mask<D, RECT>(s), b); }
-template <int D, bool RECT>
+template <int D, int SH>
+constexpr int g3_ntiles_of(int s) { return g3_rank<D, SH>(s, g3_tiles<SH>(D)); }
+template <int D, int SH>
+constexpr bool g3_uses_block(int s, int b) { return g3_touches<SH>(D, g3_mask<D, SH>(s), b); }
+template <int D, int SH>
 constexpr bool g3_owns_sums(int s, int b)
 {
-    return kG3Split<D, RECT>.sum_owner[b] == s;
+    return kG3Split<D, SH>.sum_owner[b] == s;
 }
 // Order in which a wave unpacks its blocks within a K step: greedily the
 // block that completes the most MFMA work with the blocks already unpacked
 // (ties: the lower block), so that MFMAs start early and the later blocks'
 // unpacking runs under them.  pos < 0 for a block the wave does not read.
-template <int D, bool RECT>
+template <int D, int SH>
 constexpr int g3_block_pos(int s, int b)
 {
-    constexpr int NB = g3_blocks<RECT>(D);
-    if (!g3_uses_block<D, RECT>(s, b))
+    constexpr int NB = g3_blocks<SH>(D);
+    if (!g3_uses_block<D, SH>(s, b))
         return -1;
     bool done[8] = {};
     for (int p = 0; p < NB; ++p) {
         int best = -1, best_gain = -1;
         for (int c = 0; c < NB; ++c) {
-            if (done[c] || !g3_uses_block<D, RECT>(s, c))
+            if (done[c] || !g3_uses_block<D, SH>(s, c))
                 continue;
             int gain = 0;
-            for (int t = 0; t < g3_tiles<RECT>(D); ++t) {
-                const int r = g3_row<RECT>(D, t), k = g3_col<RECT>(D, t);
-                if (g3_has<D, RECT>(s, t) && (r == c || k == c)) {
+            for (int t = 0; t < g3_tiles<SH>(D); ++t) {
+                const int r = g3_row<SH>(D, t), k = g3_col<SH>(D, t);
+                if (g3_has<D, SH>(s, t) && (r == c || k == c)) {
                     const int o = r == c ? k : r;
                     if (o == c || done[o])
-                        gain += g3_units<RECT>(D, t);
+                        gain += g3_units<SH>(D, t);
                 }
             }
             if (gain > best_gain) {
@@ -226,50 +236,53 @@ constexpr int g3_block_pos(int s, int b)
     return -1;
 }
 // a tile's MFMAs go right after the later of its two blocks is unpacked
-template <int D, bool RECT>
+template <int D, int SH>
 constexpr int g3_tile_pos(int s, int t)
 {
-    const int a = g3_block_pos<D, RECT>(s, g3_row<RECT>(D, t)), b = g3_block_pos<D, RECT>(s, g3_col<RECT>(D, t));
+    const int a = g3_block_pos<D, SH>(s, g3_row<SH>(D, t)), b = g3_block_pos<D, SH>(s, g3_col<SH>(D, t));
     return a > b ? a : b;
 }
-template <int D, bool RECT>
+template <int D, int SH>
 constexpr int g3_mfmas_of(int s)
 {
     int n = 0;
-    for (int t = 0; t < g3_tiles<RECT>(D); ++t)
-        if (g3_has<D, RECT>(s, t))
-            n += g3_units<RECT>(D, t);
+    for (int t = 0; t < g3_tiles<SH>(D); ++t)
+        if (g3_has<D, SH>(s, t))
+            n += g3_units<SH>(D, t);
     return n;
 }
 
 // LDS transpose slot of a diagonal tile: its block
-constexpr int g3_diag_slot(int t) { return tri_I(t); }
+template <int D, int SH>
+constexpr int g3_diag_slot(int t) { return g3_row<SH>(D, t); }
 
 // ---- resources ---------------------------------------------------------------
 
 // two work-groups per CU for small triangles (128 registers per wave); a
-// rectangle's 2D blocks of operands need the full 256
-template <bool RECT>
-constexpr int g3_wgs_per_cu(int D) { return !RECT && D <= 3 ? 2 : 1; }
+// rectangle's or a channel pair's 2D blocks of operands need the full 256
+template <int SH>
+constexpr int g3_wgs_per_cu(int D) { return SH == kTri && D <= 3 ? 2 : 1; }
 // waves of this kernel per SIMD
-template <bool RECT>
-constexpr int g3_waves_per_eu(int D) { return g3_wgs_per_cu<RECT>(D) * kG3Waves / 4; }
-template <bool RECT>
-constexpr int g3_nbuf(int D) { return g3_wgs_per_cu<RECT>(D) == 2 ? 4 : 8; }
+template <int SH>
+constexpr int g3_waves_per_eu(int D) { return g3_wgs_per_cu<SH>(D) * kG3Waves / 4; }
+// ring slots: 8 (4 with two work-groups per CU; 7 for a pair of 4-block
+// triangles, whose 8 transpose tiles would not fit beside 8)
+template <int SH>
+constexpr int g3_nbuf(int D) { return g3_wgs_per_cu<SH>(D) == 2 ? 4 : SH == kPair && D >= 4 ? 7 : 8; }
 constexpr int kG3Chunk = 64;                             // time rows per ring slot
 #ifndef XC_G3_CPB
 #define XC_G3_CPB 2
 #endif
 constexpr int kG3ChunksPerBarrier = XC_G3_CPB;             // chunks per work-group barrier
 constexpr int kG3TileStride = 33;                        // ints per row of a transpose tile
-template <bool RECT>
-constexpr int g3_ring_bytes(int D) { return g3_nbuf<RECT>(D) * kG3Chunk * kRowBytes; }
-template <bool RECT>
-constexpr int g3_tr_bytes(int D) { return RECT ? 0 : D * 32 * kG3TileStride * 4; }
-template <bool RECT>
-constexpr int g3_gh_bytes(int D) { return g3_blocks<RECT>(D) * 32 * 8; }
-template <bool RECT>
-constexpr int g3_smem_bytes(int D) { return g3_ring_bytes<RECT>(D) + g3_tr_bytes<RECT>(D) + g3_gh_bytes<RECT>(D); }
+template <int SH>
+constexpr int g3_ring_bytes(int D) { return g3_nbuf<SH>(D) * kG3Chunk * kRowBytes; }
+template <int SH>
+constexpr int g3_tr_bytes(int D) { return SH == kRect ? 0 : g3_blocks<SH>(D) * 32 * kG3TileStride * 4; }
+template <int SH>
+constexpr int g3_gh_bytes(int D) { return g3_blocks<SH>(D) * 32 * 8; }
+template <int SH>
+constexpr int g3_smem_bytes(int D) { return g3_ring_bytes<SH>(D) + g3_tr_bytes<SH>(D) + g3_gh_bytes<SH>(D); }
 
 // LDS-only wait: outstanding LDS operations of this wave done, memory
 // operations in flight left alone (vmcnt and expcnt at their maxima).
@@ -287,20 +300,26 @@ struct G3Args {
     const uint8_t *volts;   // [T][F][N] packed (MB = 0)
     int64_t T;              // samples (MB = 1: n_blocks * cpb * 64)
     int F, N;
-    int nreg;               // regions of this launch's shape per channel
-    int per;                // items (channel, region) per XCD range
+    int nreg;               // regions of this launch's shape per channel (or channel pair)
+    int per;                // items (channel or channel pair, region) per XCD range
     int2 *out;              // [F][P] results
     const int2 *in;         // [F][P] running sums (ACC = 1)
     int mrow0, mrows;       // work-group rows (blockIdx / 8) that serve these items
 };
 
+// Items of a launch of shape SH: (channel, region), or (channel pair, region)
+// for SH = kPair, the last pair of an odd F holding one channel.
+template <int SH>
+__host__ __device__ __forceinline__ int g3_items(int F, int nreg) { return (SH == kPair ? (F + 1) / 2 : F) * nreg; }
+
 // First global block of a region's rows and of its columns: triangle r of a
-// channel starts at block D r; rectangle k (k-th pair a > b in row-major
-// order) has rows from segment a and columns from segment b.
-template <int D, bool RECT>
+// channel (or of a channel pair) starts at block D r; rectangle k (k-th pair
+// a > b in row-major order) has rows from segment a and columns from segment
+// b.
+template <int D, int SH>
 __device__ __forceinline__ void g3_region_origin(int r, int &rb, int &cb)
 {
-    if constexpr (!RECT) {
+    if constexpr (SH != kRect) {
         rb = cb = D * r;
     } else {
         int a = (int)((1.f + sqrtf(1.f + 8.f * r)) * 0.5f);
@@ -317,21 +336,21 @@ __device__ __forceinline__ void g3_region_origin(int r, int &rb, int &cb)
 // work-group, K loop over the continuous chunk stream, and the epilogue of
 // each item.  ACC: 0 stores the sums of this launch, 1 adds the running sums
 // of `in`.
-template <int D, bool RECT, int SLOT, int ACC, int MB>
+template <int D, int SH, int SLOT, int ACC, int MB>
 __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const BlockTable *bt,
                                         const uint8_t *__restrict__ volts)
 {
-    constexpr int NBUF = g3_nbuf<RECT>(D);
+    constexpr int NBUF = g3_nbuf<SH>(D);
     constexpr int KC = kG3Chunk;
     constexpr int BUF = KC * kRowBytes;
     constexpr int LOADS = KC * 16 / kG3Threads;         // 16-byte DMA units per lane per chunk
-    constexpr int NTT = g3_tiles<RECT>(D);
-    constexpr int NB = g3_blocks<RECT>(D);
-    constexpr int NT = g3_ntiles_of<D, RECT>(SLOT) > 0 ? g3_ntiles_of<D, RECT>(SLOT) : 1;
+    constexpr int NTT = g3_tiles<SH>(D);
+    constexpr int NB = g3_blocks<SH>(D);
+    constexpr int NT = g3_ntiles_of<D, SH>(SLOT) > 0 ? g3_ntiles_of<D, SH>(SLOT) : 1;
 
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
-    if constexpr (g3_waves_per_eu<RECT>(D) == 1) {
+    if constexpr (g3_waves_per_eu<SH>(D) == 1) {
         // an AGPR operand in the function makes the compiler take the MFMA
         // forms that accumulate in AGPRs (with one wave per SIMD it then
         // has 256 of each)
@@ -341,14 +360,14 @@ __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const Bl
     const int lane = tid & 63;
     const int g = lane >> 4, q = lane & 15;
     lds_u8 *const ring = (lds_u8 *)smem;
-    int *const trs = (int *)(smem + g3_ring_bytes<RECT>(D));                             // transpose tiles
-    int *const gh = (int *)(smem + g3_ring_bytes<RECT>(D) + g3_tr_bytes<RECT>(D));      // g, h per local input
+    int *const trs = (int *)(smem + g3_ring_bytes<SH>(D));                             // transpose tiles
+    int *const gh = (int *)(smem + g3_ring_bytes<SH>(D) + g3_tr_bytes<SH>(D));      // g, h per local input
 
     // this work-group's items (channel, region): the local items m, m + M, ...
     // of its XCD's range of consecutive items
     const int xcd = blockIdx.x & 7, m = (int)(blockIdx.x >> 3) - a.mrow0, M = a.mrows;
     const int r0 = xcd * a.per;
-    const int rlen = min(a.per, a.F * a.nreg - r0);
+    const int rlen = min(a.per, g3_items<SH>(a.F, a.nreg) - r0);
     const int n_my = rlen > m ? (rlen - m + M - 1) / M : 0;
     const int nch = (int)((a.T + KC - 1) / KC);
     const int total = n_my * nch;
@@ -360,15 +379,18 @@ __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const Bl
 
     // DMA share of this wave: unit U = (SLOT * LOADS + k) * 64 + lane of a
     // chunk -> time row U / 16, position U % 16 (swizzled unit p); units
-    // 0 .. 2D-1 hold the region's row blocks, 2D .. 4D-1 (rectangles) its
-    // column blocks; the lane offsets of an item are recomputed when the
-    // issue pointer reaches it, so nothing is held across the K loop for them
+    // 0 .. 2D-1 hold the region's row blocks, 2D .. 4D-1 its column blocks
+    // (rectangles) or the same blocks of the next channel (channel pairs);
+    // the lane offsets of an item are recomputed when the issue pointer
+    // reaches it, so nothing is held across the K loop for them
     auto dma_offset = [&](int k, int f, int rb, int cb) {
         const int U = (SLOT * LOADS + k) * 64 + lane;
         const int r = U >> 4;
         const int p = (U & 15) ^ ((r & 7) << 1);
-        const int byte = p < 2 * D ? 32 * rb + 16 * p : 32 * cb + 16 * (p - 2 * D);
-        return p < 2 * NB && byte < a.N ? (int)(r * row_bytes) + f * a.N + byte : kBufferOutOfRange;
+        const bool hi = p >= 2 * D;
+        const int fo = SH == kPair && hi ? f + 1 : f;
+        const int byte = !hi ? 32 * rb + 16 * p : 32 * (SH == kPair ? rb : cb) + 16 * (p - 2 * D);
+        return p < 2 * NB && byte < a.N && fo < a.F ? (int)(r * row_bytes) + fo * a.N + byte : kBufferOutOfRange;
     };
     // operand read offsets (see frag_tr8): row (g >> 1) * 16 + (q >> 1) of the
     // K step, unit 2b + (g & 1) swizzled
@@ -383,12 +405,12 @@ __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const Bl
     int voff[LOADS];
     auto set_issue_item = [&](int k) {
         const int it = r0 + m + k * M;
-        const int f = it / a.nreg;
+        const int fq = it / a.nreg;
         int rb, cb;
-        g3_region_origin<D, RECT>(it - f * a.nreg, rb, cb);
+        g3_region_origin<D, SH>(it - fq * a.nreg, rb, cb);
 #pragma unroll
         for (int u = 0; u < LOADS; ++u)
-            voff[u] = dma_offset(u, f, rb, cb);
+            voff[u] = dma_offset(u, SH == kPair ? 2 * fq : fq, rb, cb);
     };
     set_issue_item(0);
     auto issue_next = [&](int bufi) {
@@ -409,7 +431,7 @@ __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const Bl
 #pragma unroll
         for (int k = 0; k < LOADS; ++k)
             __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (__attribute__((address_space(3))) void *)(dst + k * 1024),
-                                                     16, voff[k], 0, 0, RECT ? kSharedLoadPolicy : kStreamLoadPolicy);
+                                                     16, voff[k], 0, 0, SH == kRect ? kSharedLoadPolicy : kStreamLoadPolicy);
         if (++is_c == nch) {
             is_c = 0;
             if (++is_k < n_my)
@@ -444,20 +466,21 @@ __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const Bl
     auto read_step = [&](lds_u8 *cb, int koff, v4i *X) {
         static_for<0, NB>([&](auto bc) {
             constexpr int b = bc;
-            if constexpr (g3_uses_block<D, RECT>(SLOT, b))
+            if constexpr (g3_uses_block<D, SH>(SLOT, b))
                 X[b] = frag_tr8<8 * kRowBytes>(cb + colo[b] + koff);
         });
     };
     // epilogue of one item (channel, region): combine, descale and store this
     // wave's tiles
     auto epilogue = [&](int it) {
-        const int f = it / a.nreg;
+        const int fq = it / a.nreg;
+        const int f = SH == kPair ? 2 * fq : fq;   // first channel of the item
         int rb, cb;
-        g3_region_origin<D, RECT>(it - f * a.nreg, rb, cb);
+        g3_region_origin<D, SH>(it - fq * a.nreg, rb, cb);
         // per-input sums: lanes l and l + 32 hold the two K halves of input l % 32
         static_for<0, NB>([&](auto bc) {
             constexpr int b = bc;
-            if constexpr (g3_owns_sums<D, RECT>(SLOT, b)) {
+            if constexpr (g3_owns_sums<D, SH>(SLOT, b)) {
                 const int szl = sz[b] + sz2[b], sll = sl[b] + sl2[b];
                 const uint32_t szt = (uint32_t)(szl + __shfl_xor(szl, 32));
                 const uint32_t slt = (uint32_t)(sll + __shfl_xor(sll, 32));
@@ -472,24 +495,30 @@ __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const Bl
         wait_lgkm0();
         barrier_no_fence();
         const int64_t P = (int64_t)a.N * (a.N + 1) / 2;
-        int2 *const out_f = a.out + (int64_t)f * P;
-        const int2 *const in_f = a.in + (int64_t)f * P;
         const int jl = lane & 31;
         const int il0 = 4 * (lane >> 5);
         static_for<0, NTT>([&](auto tc) {
             constexpr int t = tc;
-            if constexpr (g3_has<D, RECT>(SLOT, t)) {
-            constexpr int q = g3_rank<D, RECT>(SLOT, t);
-            constexpr int I = g3_row<RECT>(D, t), J = g3_col<RECT>(D, t);   // local blocks
-            constexpr bool diag = g3_isdiag<RECT>(D, t);
+            if constexpr (g3_has<D, SH>(SLOT, t)) {
+            constexpr int q = g3_rank<D, SH>(SLOT, t);
+            constexpr int I = g3_row<SH>(D, t), J = g3_col<SH>(D, t);   // local blocks
+            constexpr bool diag = g3_isdiag<SH>(D, t);
+            // a channel pair's second triangle: the next channel, blocks
+            // I - D and J - D of its segment (none for the last of an odd F)
+            constexpr bool second = SH == kPair && I >= D;
+            constexpr int Ib = second ? I - D : I, Jb = second ? J - D : J;
+            const int fch = second ? f + 1 : f;
+            if (fch < a.F) {
+            int2 *const out_f = a.out + (int64_t)fch * P;
+            const int2 *const in_f = a.in + (int64_t)fch * P;
             // column input: local index for the sums, global for the output
             const int jloc = J * 32 + jl;
-            const int j = (RECT ? cb + (J - D) : rb + J) * 32 + jl;
+            const int j = (SH == kRect ? cb + (J - D) : rb + Jb) * 32 + jl;
             const int2 ghj = *(const int2 *)&gh[jloc * 2];
             v16i ba;
             if constexpr (diag) {
                 // P_ba of a diagonal tile is the transpose of its P_ab
-                int *const tr = trs + g3_diag_slot(t) * 32 * kG3TileStride;
+                int *const tr = trs + g3_diag_slot<D, SH>(t) * 32 * kG3TileStride;
 #pragma unroll
                 for (int r = 0; r < 16; ++r)
                     tr[(8 * (r >> 2) + il0 + (r & 3)) * kG3TileStride + jl] = acc_ab[q][r];
@@ -501,8 +530,8 @@ __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const Bl
             }
 #pragma unroll
             for (int r4 = 0; r4 < 4; ++r4) {
-                const int ibl = I * 32 + 8 * r4 + il0;    // rows ibl .. ibl + 3 (local)
-                const int ib = rb * 32 + ibl;             // and their global inputs
+                const int ibl = I * 32 + 8 * r4 + il0;                // rows ibl .. ibl + 3 (local)
+                const int ib = (rb + Ib) * 32 + 8 * r4 + il0;         // and their global inputs
                 // running sums of these rows (ACC = 1), from a valid address
                 // where the pair does not exist
                 int2 old[4];
@@ -537,6 +566,7 @@ __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const Bl
                 }
             }
             }
+            }
         });
     };
 
@@ -568,11 +598,11 @@ __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const Bl
             constexpr int k = kc;
             static_for<0, NB>([&](auto bc) {
                 constexpr int b = bc;
-                if constexpr (g3_block_pos<D, RECT>(SLOT, b) == k) {
+                if constexpr (g3_block_pos<D, SH>(SLOT, b) == k) {
                     A[b] = X[b] ^ 0x08080808;
                     B[b] = X[b] ^ 0x07070707;
                     R[b] = X[b] & (int)0xF0F0F0F0;
-                    if constexpr (g3_owns_sums<D, RECT>(SLOT, b)) {
+                    if constexpr (g3_owns_sums<D, SH>(SLOT, b)) {
 #pragma unroll
                         for (int k = 0; k < 4; ++k) {
                             int &z = k & 1 ? sz2[b] : sz[b];
@@ -585,17 +615,17 @@ __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const Bl
             });
             static_for<0, NTT>([&](auto tc) {
                 constexpr int t = tc;
-                if constexpr (g3_has<D, RECT>(SLOT, t) && g3_tile_pos<D, RECT>(SLOT, t) == k) {
-                    constexpr int q = g3_rank<D, RECT>(SLOT, t);
-                    constexpr int I = g3_row<RECT>(D, t), J = g3_col<RECT>(D, t);
+                if constexpr (g3_has<D, SH>(SLOT, t) && g3_tile_pos<D, SH>(SLOT, t) == k) {
+                    constexpr int q = g3_rank<D, SH>(SLOT, t);
+                    constexpr int I = g3_row<SH>(D, t), J = g3_col<SH>(D, t);
                     acc_ab[q] = mfma_i8(A[I], B[J], acc_ab[q]);
-                    if constexpr (!g3_isdiag<RECT>(D, t))
+                    if constexpr (!g3_isdiag<SH>(D, t))
                         acc_ba[q] = mfma_i8(B[I], A[J], acc_ba[q]);
                     acc_rr[q] = mfma_i8(R[I], R[J], acc_rr[q]);
                 }
             });
         });
-        static_for<0, g3_mfmas_of<D, RECT>(SLOT)>([&](auto) {
+        static_for<0, g3_mfmas_of<D, SH>(SLOT)>([&](auto) {
             __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
             __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);   // up to six VALU
         });
@@ -656,14 +686,14 @@ __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const Bl
     }
 }
 
-template <int D, bool RECT, int ACC, int MB>
+template <int D, int SH, int ACC, int MB>
 __device__ __forceinline__ void g3_dispatch(uint8_t *smem, const G3Args &a, const BlockTable *bt)
 {
     switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {
 #define XC_CASE(W)                                              \
     case W:                                                     \
         if constexpr (W < kG3Waves)                             \
-            g3_wave<D, RECT, W, ACC, MB>(smem, a, bt, a.volts); \
+            g3_wave<D, SH, W, ACC, MB>(smem, a, bt, a.volts); \
         break;
         XC_CASE(0) XC_CASE(1) XC_CASE(2) XC_CASE(3) XC_CASE(4) XC_CASE(5) XC_CASE(6) XC_CASE(7)
         XC_CASE(8) XC_CASE(9) XC_CASE(10) XC_CASE(11) XC_CASE(12) XC_CASE(13) XC_CASE(14) XC_CASE(15)

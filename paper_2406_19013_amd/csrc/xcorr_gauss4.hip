@@ -3,19 +3,22 @@
 // (channel, region) items as one continuous stream of LDS-DMA chunks.  A
 // channel of up to 6 blocks is one triangle; more blocks (D <= 4) split into
 // triangles of D blocks on the diagonal and D x D rectangles between them,
-// run as two launches (all triangles, then all rectangles).
+// run as two launches (all triangles, then all rectangles).  Triangles of 4
+// blocks go two channels to an item (20 tiles over 8 blocks, about the work
+// of the 6-block triangle), which spreads each chunk's fixed cost over twice
+// the MFMAs.
 #include "xc_gauss4.h"
 
 namespace xc {
 namespace {
 
-template <int D, bool RECT, int ACC, int MB>
+template <int D, int SH, int ACC, int MB>
 __global__ __launch_bounds__(kG3Threads)
-__attribute__((amdgpu_waves_per_eu(g3_waves_per_eu<RECT>(D), g3_waves_per_eu<RECT>(D))))
+__attribute__((amdgpu_waves_per_eu(g3_waves_per_eu<SH>(D), g3_waves_per_eu<SH>(D))))
 void xc_gauss4_kernel(const G3Args a, const BlockTable bt)
 {
-    __shared__ __attribute__((aligned(1024))) uint8_t smem[g3_smem_bytes<RECT>(D)];
-    g3_dispatch<D, RECT, ACC, MB>(smem, a, &bt);
+    __shared__ __attribute__((aligned(1024))) uint8_t smem[g3_smem_bytes<SH>(D)];
+    g3_dispatch<D, SH, ACC, MB>(smem, a, &bt);
 }
 
 // compute units of the current device (queried once per device)
@@ -34,12 +37,12 @@ int device_cu_count()
     return cached[dev];
 }
 
-template <int D, bool RECT>
+template <int D, int SH>
 hipError_t launch_shape(const G3Args &a, const BlockTable *bt, int accumulate, hipStream_t s)
 {
-    const int64_t items = (int64_t)a.F * a.nreg;
+    const int64_t items = g3_items<SH>(a.F, a.nreg);
     const int per = (int)((items + 7) / 8);
-    const int m_max = device_cu_count() * g3_wgs_per_cu<RECT>(D) / 8;
+    const int m_max = device_cu_count() * g3_wgs_per_cu<SH>(D) / 8;
     const int grid = 8 * std::max(1, std::min(m_max, per));
     G3Args args = a;
     args.per = per;
@@ -48,8 +51,8 @@ hipError_t launch_shape(const G3Args &a, const BlockTable *bt, int accumulate, h
     BlockTable table{};
     if (bt)
         table = *bt;
-    auto kern = bt ? (accumulate ? xc_gauss4_kernel<D, RECT, 1, 1> : xc_gauss4_kernel<D, RECT, 0, 1>)
-                   : (accumulate ? xc_gauss4_kernel<D, RECT, 1, 0> : xc_gauss4_kernel<D, RECT, 0, 0>);
+    auto kern = bt ? (accumulate ? xc_gauss4_kernel<D, SH, 1, 1> : xc_gauss4_kernel<D, SH, 0, 1>)
+                   : (accumulate ? xc_gauss4_kernel<D, SH, 1, 0> : xc_gauss4_kernel<D, SH, 0, 0>);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kG3Threads), 0, s, args, table);
     return hipGetLastError();
 }
@@ -60,12 +63,16 @@ hipError_t launch_t(const G3Args &a, int nseg, const BlockTable *bt, int accumul
 {
     G3Args t = a;
     t.nreg = nseg;
-    hipError_t e = launch_shape<D, false>(t, bt, accumulate, s);
+    hipError_t e;
+    if constexpr (D == 4)
+        e = a.F >= 2 ? launch_shape<D, kPair>(t, bt, accumulate, s) : launch_shape<D, kTri>(t, bt, accumulate, s);
+    else
+        e = launch_shape<D, kTri>(t, bt, accumulate, s);
     if constexpr (D <= 4) {
         if (e == hipSuccess && nseg > 1) {
             G3Args r = a;
             r.nreg = nseg * (nseg - 1) / 2;
-            e = launch_shape<D, true>(r, bt, accumulate, s);
+            e = launch_shape<D, kRect>(r, bt, accumulate, s);
         }
     }
     return e;

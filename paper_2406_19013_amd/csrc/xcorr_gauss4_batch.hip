@@ -16,9 +16,11 @@
 namespace xc {
 namespace {
 
-// region shapes the batched launch carries: triangles of 2, 3, 4 and 6
-// blocks, rectangles of 2, 3 and 4; a job's kind is 2 * shape + accumulate
-enum G3Shape { kTri2, kTri3, kTri4, kTri6, kRect2, kRect3, kRect4 };
+// region shapes the batched launch carries: triangles of 2, 3 and 6 blocks,
+// pairs of 4-block triangles (two channels to an item; a single 4-block
+// triangle where F = 1), rectangles of 2, 3 and 4; a job's kind is
+// 2 * shape + accumulate
+enum G3Shape { kTri2, kTri3, kTri4, kTri6, kRect2, kRect3, kRect4, kPair4 };
 
 constexpr int kMaxG3Jobs = 2 * kMaxBatchArrays;
 
@@ -36,10 +38,10 @@ constexpr int g3_batch_smem_bytes()
 {
     int m = 0;
     for (int d : {2, 3, 4, 6})
-        m = std::max(m, g3_smem_bytes<false>(d));
+        m = std::max(m, g3_smem_bytes<kTri>(d));
     for (int d : {2, 3, 4})
-        m = std::max(m, g3_smem_bytes<true>(d));
-    return m;
+        m = std::max(m, g3_smem_bytes<kRect>(d));
+    return std::max(m, g3_smem_bytes<kPair>(4));
 }
 
 // The job of a work-group is picked by a run-time index, so it is read from
@@ -82,8 +84,9 @@ void xc_gauss4_batch_kernel(const G3BatchArgs b)
 #define XC_SHAPE(S, D, RECT)                                                  \
     case 2 * S: g3_dispatch<D, RECT, 0, 0>(smem, a, nullptr); break;          \
     case 2 * S + 1: g3_dispatch<D, RECT, 1, 0>(smem, a, nullptr); break;
-        XC_SHAPE(kTri2, 2, false) XC_SHAPE(kTri3, 3, false) XC_SHAPE(kTri4, 4, false) XC_SHAPE(kTri6, 6, false)
-        XC_SHAPE(kRect2, 2, true) XC_SHAPE(kRect3, 3, true) XC_SHAPE(kRect4, 4, true)
+        XC_SHAPE(kTri2, 2, kTri) XC_SHAPE(kTri3, 3, kTri) XC_SHAPE(kTri4, 4, kTri) XC_SHAPE(kTri6, 6, kTri)
+        XC_SHAPE(kRect2, 2, kRect) XC_SHAPE(kRect3, 3, kRect) XC_SHAPE(kRect4, 4, kRect)
+        XC_SHAPE(kPair4, 4, kPair)
 #undef XC_SHAPE
         default: break;
         }
@@ -96,6 +99,8 @@ void xc_gauss4_batch_kernel(const G3BatchArgs b)
 // measured chunk times of the 4- and 6-block triangles, 0.81 and 1.25 us at
 // 2048 samples; the 4-block rectangle, 1.2 us, lands within 10 %).
 int64_t chunk_cost(int D, bool rect) { return 31 + (rect ? 3LL * D * D : 3LL * D * (D - 1) / 2 + 2LL * D); }
+// a pair item: both channels' MFMAs, one chunk's fixed cost
+int64_t pair_chunk_cost(int D) { return chunk_cost(D, false) + (chunk_cost(D, false) - 31); }
 
 }  // namespace
 
@@ -128,7 +133,8 @@ hipError_t launch_gauss4_batch(const BatchArgs &args, int cus, hipStream_t s)
             return hipErrorInvalidValue;
         for (int rect = 0; rect <= (A.nseg > 1 ? 1 : 0); ++rect) {
             G3Job &J = b.job[b.n];
-            const int shape = rect ? kRect2 + (A.D - 2) : (A.D == 6 ? kTri6 : kTri2 + (A.D - 2));
+            const bool pair = !rect && A.D == 4 && A.F >= 2;
+            const int shape = rect ? kRect2 + (A.D - 2) : pair ? kPair4 : (A.D == 6 ? kTri6 : kTri2 + (A.D - 2));
             J.kind = 2 * shape + (A.accumulate ? 1 : 0);
             J.a.volts = A.volts;
             J.a.T = A.T;
@@ -137,12 +143,12 @@ hipError_t launch_gauss4_batch(const BatchArgs &args, int cus, hipStream_t s)
             J.a.nreg = rect ? A.nseg * (A.nseg - 1) / 2 : A.nseg;
             J.a.out = A.acc;
             J.a.in = A.acc;
-            const int64_t items = (int64_t)A.F * J.a.nreg;
+            const int64_t items = pair ? g3_items<kPair>(A.F, J.a.nreg) : (int64_t)A.F * J.a.nreg;
             per[b.n] = (items + 7) / 8;
             J.a.per = (int)per[b.n];
             // an item: its chunks plus about four chunks' worth of epilogue
             // (the combination and the stores of its tiles)
-            work[b.n] = chunk_cost(A.D, rect) * ((A.T + 63) / 64 + 4);
+            work[b.n] = (pair ? pair_chunk_cost(A.D) : chunk_cost(A.D, rect)) * ((A.T + 63) / 64 + 4);
             ++b.n;
         }
     }
