@@ -25,8 +25,9 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libxcorr.so")
 ARCH = "gfx950"
 
-# (source, extra flags, object name).  The 8+8-bit MFMA kernels are compiled
-# once per diagonal block size so that the objects build in parallel.
+# (source, extra flags, object name).  The 8+8-bit and the three-product
+# 4+4-bit MFMA kernels are compiled once per diagonal block size so that the
+# objects build in parallel.
 UNITS = [("xcorr_kernels.hip", [], "xcorr_kernels.o"), ("xcorr_api.cpp", [], "xcorr_api.o"),
          ("xcorr_pipe.cpp", [], "xcorr_pipe.o"), ("xcorr_reorder.cpp", [], "xcorr_reorder.o"), ("xcorr_cns.cpp", [], "xcorr_cns.o"),
          ("xcorr_mfma4.hip", [], "xcorr_mfma4.o"), ("xcorr_mfma4f.hip", [], "xcorr_mfma4f.o"),
@@ -36,7 +37,8 @@ UNITS = [("xcorr_kernels.hip", [], "xcorr_kernels.o"), ("xcorr_api.cpp", [], "xc
          ("xcorr_ceiling.hip", [], "xcorr_ceiling.o"),
          ("xcorr_fengine.hip", [], "xcorr_fengine.o"),
          ("xcorr_stokes.hip", [], "xcorr_stokes.o")] + [
-    ("xcorr_mfma8.hip", [f"-DXC_D={d}"], f"xcorr_mfma8_d{d}.o") for d in range(1, 7)]
+    ("xcorr_mfma8.hip", [f"-DXC_D={d}"], f"xcorr_mfma8_d{d}.o") for d in range(1, 7)] + [
+    ("xcorr_gauss4.hip", [f"-DXC_G3_D={d}"], f"xcorr_gauss4_d{d}.o") for d in range(1, 7)]
 RESOURCES = "kernel_resources.txt"
 
 # Packed FP32 VALU ops are disabled for every device compile.

@@ -7,9 +7,21 @@
 // blocks go two channels to an item (20 tiles over 8 blocks, about the work
 // of the 6-block triangle), which spreads each chunk's fixed cost over twice
 // the MFMAs.
+//
+// The kernels are compiled in one unit per diagonal size D (XC_G3_D = 1 .. 6,
+// so that the units build in parallel), each defining gauss4_launch_d<D>; the
+// unit without XC_G3_D holds the host entry points.
 #include "xc_gauss4.h"
 
 namespace xc {
+
+// every launch for a plan with diagonal size D: the segment triangles, then
+// (several segments) the rectangles between them
+template <int D>
+hipError_t gauss4_launch_d(const uint8_t *volts, int64_t T, int F, int N, int2 *out, const int2 *in, int nseg,
+                           const BlockTable *bt, int accumulate, hipStream_t s);
+
+#ifdef XC_G3_D
 namespace {
 
 template <int D, int SH, int ACC, int MB>
@@ -57,10 +69,20 @@ hipError_t launch_shape(const G3Args &a, const BlockTable *bt, int accumulate, h
     return hipGetLastError();
 }
 
-// the triangles of every channel, then (several segments) the rectangles
-template <int D>
-hipError_t launch_t(const G3Args &a, int nseg, const BlockTable *bt, int accumulate, hipStream_t s)
+}  // namespace
+
+template <>
+hipError_t gauss4_launch_d<XC_G3_D>(const uint8_t *volts, int64_t T, int F, int N, int2 *out, const int2 *in,
+                                    int nseg, const BlockTable *bt, int accumulate, hipStream_t s)
 {
+    constexpr int D = XC_G3_D;
+    G3Args a{};
+    a.volts = volts;
+    a.T = T;
+    a.F = F;
+    a.N = N;
+    a.out = out;
+    a.in = in;
     G3Args t = a;
     t.nreg = nseg;
     hipError_t e;
@@ -78,15 +100,39 @@ hipError_t launch_t(const G3Args &a, int nseg, const BlockTable *bt, int accumul
     return e;
 }
 
-hipError_t launch_any(int D, int nseg, const G3Args &a, const BlockTable *bt, int accumulate, hipStream_t s)
+#else
+
+template <>
+hipError_t gauss4_launch_d<1>(const uint8_t *, int64_t, int, int, int2 *, const int2 *, int, const BlockTable *, int,
+                              hipStream_t);
+template <>
+hipError_t gauss4_launch_d<2>(const uint8_t *, int64_t, int, int, int2 *, const int2 *, int, const BlockTable *, int,
+                              hipStream_t);
+template <>
+hipError_t gauss4_launch_d<3>(const uint8_t *, int64_t, int, int, int2 *, const int2 *, int, const BlockTable *, int,
+                              hipStream_t);
+template <>
+hipError_t gauss4_launch_d<4>(const uint8_t *, int64_t, int, int, int2 *, const int2 *, int, const BlockTable *, int,
+                              hipStream_t);
+template <>
+hipError_t gauss4_launch_d<5>(const uint8_t *, int64_t, int, int, int2 *, const int2 *, int, const BlockTable *, int,
+                              hipStream_t);
+template <>
+hipError_t gauss4_launch_d<6>(const uint8_t *, int64_t, int, int, int2 *, const int2 *, int, const BlockTable *, int,
+                              hipStream_t);
+
+namespace {
+
+hipError_t launch_any(int D, int nseg, const uint8_t *volts, int64_t T, int F, int N, int2 *out, const int2 *in,
+                      const BlockTable *bt, int accumulate, hipStream_t s)
 {
     switch (D) {
-    case 1: return launch_t<1>(a, nseg, bt, accumulate, s);
-    case 2: return launch_t<2>(a, nseg, bt, accumulate, s);
-    case 3: return launch_t<3>(a, nseg, bt, accumulate, s);
-    case 4: return launch_t<4>(a, nseg, bt, accumulate, s);
-    case 5: return launch_t<5>(a, nseg, bt, accumulate, s);
-    case 6: return launch_t<6>(a, nseg, bt, accumulate, s);
+    case 1: return gauss4_launch_d<1>(volts, T, F, N, out, in, nseg, bt, accumulate, s);
+    case 2: return gauss4_launch_d<2>(volts, T, F, N, out, in, nseg, bt, accumulate, s);
+    case 3: return gauss4_launch_d<3>(volts, T, F, N, out, in, nseg, bt, accumulate, s);
+    case 4: return gauss4_launch_d<4>(volts, T, F, N, out, in, nseg, bt, accumulate, s);
+    case 5: return gauss4_launch_d<5>(volts, T, F, N, out, in, nseg, bt, accumulate, s);
+    case 6: return gauss4_launch_d<6>(volts, T, F, N, out, in, nseg, bt, accumulate, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -107,14 +153,7 @@ hipError_t launch_gauss4(const Plan &pl, const uint8_t *volts, int64_t T, int F,
     if (!gauss4_supported(pl, F, N) || T < 1 || T > kMaxSamplesPerLaunch4 || !volts || (uintptr_t)volts % 16 ||
         !acc)
         return hipErrorInvalidValue;
-    G3Args a{};
-    a.volts = volts;
-    a.T = T;
-    a.F = F;
-    a.N = N;
-    a.out = acc;
-    a.in = acc_in ? acc_in : acc;
-    return launch_any(pl.D, pl.nseg, a, nullptr, accumulate, s);
+    return launch_any(pl.D, pl.nseg, volts, T, F, N, acc, acc_in ? acc_in : acc, nullptr, accumulate, s);
 }
 
 hipError_t launch_gauss4_blocks(const Plan &pl, const BlockTable &bt, int n_blocks, int F, int N, int2 *acc,
@@ -126,14 +165,10 @@ hipError_t launch_gauss4_blocks(const Plan &pl, const BlockTable &bt, int n_bloc
     for (int b = 0; b < n_blocks; ++b)
         if (!bt.p[b] || (uintptr_t)bt.p[b] % 16)
             return hipErrorInvalidValue;
-    G3Args a{};
-    a.volts = bt.p[0];
-    a.T = (int64_t)n_blocks * bt.chunks_per_block * 64;
-    a.F = F;
-    a.N = N;
-    a.out = acc;
-    a.in = acc_in ? acc_in : acc;
-    return launch_any(pl.D, pl.nseg, a, &bt, accumulate, s);
+    return launch_any(pl.D, pl.nseg, bt.p[0], (int64_t)n_blocks * bt.chunks_per_block * 64, F, N, acc,
+                      acc_in ? acc_in : acc, &bt, accumulate, s);
 }
+
+#endif
 
 }  // namespace xc
