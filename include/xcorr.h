@@ -180,13 +180,16 @@ int xcorr_stats(const xcorr_ctx *ctx, xcorr_stats_t *out);
 int xcorr_destroy(xcorr_ctx *ctx);
 
 /*
- * Batched persistent launch (4+4-bit, int8-MFMA contexts only).  The X-engine
- * of Section 2.3 runs once per array; a batch correlates up to
- * XCORR_MAX_BATCH arrays of uneven N, F and sample count in one kernel that
- * drains a work queue of (array, channel, region) items.  Results, the
- * integration bookkeeping and the dumps stay per context (xcorr_dump).
+ * Batched launch (4+4-bit, int8-MFMA contexts only).  The X-engine of
+ * Section 2.3 runs once per array; a batch correlates up to XCORR_MAX_BATCH
+ * arrays of uneven N, F and sample count in one kernel launch.  Where every
+ * array has N a multiple of 16 and a 16-byte-aligned input, each array's
+ * region shapes are jobs of the three-product kernel that every work-group
+ * walks in turn; otherwise one kernel drains a work queue of (array,
+ * channel, region) items.  Results, the integration bookkeeping and the
+ * dumps stay per context (xcorr_dump).
  *
- * xcorr_batch_query: device bytes the batch needs (its work-queue counters).
+ * xcorr_batch_query: device bytes the batch needs (the work-queue counters).
  * xcorr_batch_init : ctxs[0..n) are borrowed (they must outlive the batch and
  *   keep their workspaces); d_workspace (>= the queried size, 256-byte
  *   aligned) is borrowed until xcorr_batch_destroy and is initialised here
@@ -201,8 +204,9 @@ int xcorr_destroy(xcorr_ctx *ctx);
  *   array's sequence then continues without a gap).  Checks, before anything
  *   is enqueued: XCORR_E_INVAL (NULL arrays, negative counts, all counts 0),
  *   XCORR_E_OVERFLOW if any array would pass its max_samples_per_dump.  Every
- *   launch leaves the queue counters as it found them, so an ingest can be
- *   captured in a HIP graph and replayed; a replay repeats the overwrite /
+ *   launch leaves the queue counters as it found them (the three-product
+ *   launch uses none), so an ingest can be captured in a HIP graph and
+ *   replayed; a replay repeats the overwrite /
  *   accumulate choice made at capture, so capture whole integrations (the
  *   first ingest after a dump through the dump).  Launches of one batch must
  *   not overlap (one stream at a time).
