@@ -477,6 +477,12 @@ __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const Bl
         const int f = SH == kPair ? 2 * fq : fq;   // first channel of the item
         int rb, cb;
         g3_region_origin<D, SH>(it - fq * a.nreg, rb, cb);
+        // every wave has read the previous item's g and h before they are
+        // overwritten: the group barriers of the K loop need not fall between
+        // two epilogues (an item of at most CPB chunks that ends the
+        // work-group's stream has none)
+        wait_lgkm0();
+        barrier_no_fence();
         // per-input sums: lanes l and l + 32 hold the two K halves of input l % 32
         static_for<0, NB>([&](auto bc) {
             constexpr int b = bc;

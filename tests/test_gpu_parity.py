@@ -253,6 +253,22 @@ def test_persistent_workgroups_walk_many_regions(N, F, tile):
     assert np.array_equal(got[chans], ref)
 
 
+SHORT = [(192, 700, 6, 64), (256, 300, 4, 96), (128, 900, 4, 128), (96, 1400, 3, 100), (512, 60, 4, 64)]
+
+
+@pytest.mark.parametrize("N,F,tile,T", SHORT, ids=[f"N{n}F{f}D{d}T{t}" for n, f, d, t in SHORT])
+def test_short_launches_with_many_items_per_workgroup(N, F, tile, T):
+    """Launches of at most two 64-sample chunks, several items per
+    work-group: consecutive epilogues with no group barrier of the K loop
+    between them must not overwrite each other's per-input sums (every
+    channel checked, three launches)."""
+    _say(f"short launches N={N} F={F} D={tile} T={T}")
+    v = synth.uniform_volts4(N, F, T, seed=(1011, N, F, T))
+    want = expected(v, N, F)
+    for _ in range(3):
+        assert np.array_equal(gpu_correlate(v, N, F, 4, X.PATH_I8_MFMA, tile), want)
+
+
 @pytest.mark.parametrize("N,F,splits", [(192, 4, [300]), (64, 3, [100, 129]), (100, 2, [64, 77]),
                                          (16, 1, [140_001])],
                          ids=["one_ingest", "after_ingest", "ragged_inputs", "launch_split"])
