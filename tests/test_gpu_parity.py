@@ -87,18 +87,19 @@ def test_every_tile_shape_bit_exact(N, tile, variant, monkeypatch):
     assert np.array_equal(got, expected(v, N, F))
 
 
-# tile 4 runs its triangles two channels to an item: an odd F leaves the
-# last item one channel; F = 1 runs single triangles
-PAIRS = [(128, 3), (128, 1), (96, 2), (208, 5), (256, 3), (512, 3)]
+# tiles 3 and 4 run their triangles two channels to an item: an odd F
+# leaves the last item one channel; F = 1 runs single triangles
+PAIRS = [(128, 3, 4), (128, 1, 4), (96, 2, 4), (208, 5, 4), (256, 3, 4), (512, 3, 4),
+         (96, 3, 3), (96, 1, 3), (80, 2, 3), (288, 5, 3), (208, 3, 3)]
 
 
-@pytest.mark.parametrize("N,F", PAIRS, ids=[f"N{n}F{f}" for n, f in PAIRS])
-def test_channel_pairs_of_4_block_triangles(N, F):
+@pytest.mark.parametrize("N,F,tile", PAIRS, ids=[f"N{n}F{f}D{d}" for n, f, d in PAIRS])
+def test_channel_pairs_of_small_triangles(N, F, tile):
     T = 150
-    _say(f"channel pairs N={N} F={F}")
+    _say(f"channel pairs N={N} F={F} D={tile}")
     v = synth.uniform_volts4(N, F, T, seed=(1010, N, F))
     # two ingests: the second launch adds to the first's sums
-    got = gpu_correlate(v, N, F, 4, X.PATH_I8_MFMA, 4, splits=[64, 86])
+    got = gpu_correlate(v, N, F, 4, X.PATH_I8_MFMA, tile, splits=[64, 86])
     assert np.array_equal(got, expected(v, N, F))
 
 
