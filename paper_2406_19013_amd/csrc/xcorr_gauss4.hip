@@ -3,8 +3,8 @@
 // (channel, region) items as one continuous stream of LDS-DMA chunks.  A
 // channel of up to 6 blocks is one triangle; more blocks (D <= 4) split into
 // triangles of D blocks on the diagonal and D x D rectangles between them,
-// run as two launches (all triangles, then all rectangles).  Triangles of 3
-// and 4 blocks go two channels to an item (12 or 20 tiles over 6 or 8
+// run as two launches (all triangles, then all rectangles).  Triangles of 2
+// to 4 blocks go two channels to an item (6, 12 or 20 tiles over 4, 6 or 8
 // blocks), which spreads each chunk's fixed cost over twice the MFMAs.
 //
 // The kernels are compiled in one unit per diagonal size D (XC_G3_D = 1 .. 6,
@@ -85,7 +85,7 @@ hipError_t gauss4_launch_d<XC_G3_D>(const uint8_t *volts, int64_t T, int F, int 
     G3Args t = a;
     t.nreg = nseg;
     hipError_t e;
-    if constexpr (D == 3 || D == 4)
+    if constexpr (D >= 2 && D <= 4)
         e = a.F >= 2 ? launch_shape<D, kPair>(t, bt, accumulate, s) : launch_shape<D, kTri>(t, bt, accumulate, s);
     else
         e = launch_shape<D, kTri>(t, bt, accumulate, s);

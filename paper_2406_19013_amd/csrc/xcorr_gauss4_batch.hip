@@ -16,11 +16,11 @@
 namespace xc {
 namespace {
 
-// region shapes the batched launch carries: triangles of 2 and 6 blocks,
-// pairs of 3- and 4-block triangles (two channels to an item; single
-// triangles where F = 1), rectangles of 2, 3 and 4; a job's kind is
-// 2 * shape + accumulate
-enum G3Shape { kTri2, kTri3, kTri4, kTri6, kRect2, kRect3, kRect4, kPair3, kPair4 };
+// region shapes the batched launch carries: triangles of 6 blocks, pairs of
+// 2-, 3- and 4-block triangles (two channels to an item; single triangles
+// where F = 1), rectangles of 2, 3 and 4; a job's kind is 2 * shape +
+// accumulate
+enum G3Shape { kTri2, kTri3, kTri4, kTri6, kRect2, kRect3, kRect4, kPair2, kPair3, kPair4 };
 
 constexpr int kMaxG3Jobs = 2 * kMaxBatchArrays;
 
@@ -41,7 +41,9 @@ constexpr int g3_batch_smem_bytes()
         m = std::max(m, g3_smem_bytes<kTri>(d));
     for (int d : {2, 3, 4})
         m = std::max(m, g3_smem_bytes<kRect>(d));
-    return std::max(m, std::max(g3_smem_bytes<kPair>(3), g3_smem_bytes<kPair>(4)));
+    for (int d : {2, 3, 4})
+        m = std::max(m, g3_smem_bytes<kPair>(d));
+    return m;
 }
 
 // The job of a work-group is picked by a run-time index, so it is read from
@@ -86,7 +88,7 @@ void xc_gauss4_batch_kernel(const G3BatchArgs b)
     case 2 * S + 1: g3_dispatch<D, RECT, 1, 0>(smem, a, nullptr); break;
         XC_SHAPE(kTri2, 2, kTri) XC_SHAPE(kTri3, 3, kTri) XC_SHAPE(kTri4, 4, kTri) XC_SHAPE(kTri6, 6, kTri)
         XC_SHAPE(kRect2, 2, kRect) XC_SHAPE(kRect3, 3, kRect) XC_SHAPE(kRect4, 4, kRect)
-        XC_SHAPE(kPair3, 3, kPair) XC_SHAPE(kPair4, 4, kPair)
+        XC_SHAPE(kPair2, 2, kPair) XC_SHAPE(kPair3, 3, kPair) XC_SHAPE(kPair4, 4, kPair)
 #undef XC_SHAPE
         default: break;
         }
@@ -133,9 +135,9 @@ hipError_t launch_gauss4_batch(const BatchArgs &args, int cus, hipStream_t s)
             return hipErrorInvalidValue;
         for (int rect = 0; rect <= (A.nseg > 1 ? 1 : 0); ++rect) {
             G3Job &J = b.job[b.n];
-            const bool pair = !rect && (A.D == 3 || A.D == 4) && A.F >= 2;
+            const bool pair = !rect && A.D >= 2 && A.D <= 4 && A.F >= 2;
             const int shape = rect ? kRect2 + (A.D - 2)
-                              : pair ? kPair3 + (A.D - 3)
+                              : pair ? kPair2 + (A.D - 2)
                                      : (A.D == 6 ? kTri6 : kTri2 + (A.D - 2));
             J.kind = 2 * shape + (A.accumulate ? 1 : 0);
             J.a.volts = A.volts;

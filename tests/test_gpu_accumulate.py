@@ -64,8 +64,8 @@ def test_accumulating_launches_match_oracle(N, F, tile, splits):
     c.close()
 
 
-@pytest.mark.parametrize("N,F,tile", [(512, 4, 4), (256, 3, 4), (96, 3, 3), (192, 6, 6), (160, 3, 5)],
-                         ids=["N512D4", "N256D4F3", "N96D3F3", "N192D6", "N160D5"])
+@pytest.mark.parametrize("N,F,tile", [(512, 4, 4), (256, 3, 4), (96, 3, 3), (64, 5, 2), (192, 6, 6), (160, 3, 5)],
+                         ids=["N512D4", "N256D4F3", "N96D3F3", "N64D2F5", "N192D6", "N160D5"])
 def test_fused_blocks_accumulate_across_groups(N, F, tile):
     """Ten 128-sample device blocks in groups of at most 8 per launch (the
     second group adds to the first group's sums) against the oracle."""

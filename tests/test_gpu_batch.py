@@ -88,17 +88,18 @@ def test_batch_every_region_shape(tmp_path, monkeypatch):
                      "4 128 2 1 4 xc_gauss4_batch_kernel\n"
                      "4 256 3 1 4 xc_gauss4_batch_kernel\n")
     monkeypatch.setenv("XCORR_TUNE_CACHE", str(cache))
-    # 3- and 4-block triangles go two channels to an item; 256 x 3 and
-    # 288 x 3 leave the last item one channel, 96 x 1 runs a single triangle
+    # 2- to 4-block triangles go two channels to an item; 256 x 3, 288 x 3
+    # and 48 x 3 leave the last item one channel, 96 x 1, 64 x 1 and 160 x 1
+    # run single triangles
     arrays = [(320, 2, 150), (288, 3, 100), (208, 2, 90), (128, 2, 70), (96, 2, 64), (160, 1, 33), (48, 3, 129),
-              (256, 3, 77), (96, 1, 50)]
+              (256, 3, 77), (96, 1, 50), (64, 1, 40)]
     _say(f"batch region shapes {arrays}")
     assert [X.xcorr_autotune_kernel(X.make_config(N, F, 4, X.PATH_I8_MFMA), batch=True)
             for N, F, _ in arrays] == ["xc_gauss4_batch_kernel"] * len(arrays)
     vs = [synth.uniform_volts4(N, F, T, seed=(3008, N, F, T)) for N, F, T in arrays]
     cors = [X.Correlator(N, F, 4, X.PATH_I8_MFMA) for N, F, _ in arrays]
     b = X.Batch(cors)
-    assert b.tiles == [2, 3, 4, 4, 3, 6, 2, 4, 3], b.tiles
+    assert b.tiles == [2, 3, 4, 4, 3, 6, 2, 4, 3, 2], b.tiles
     b.ingest([v.cuda() for v in vs])
     for (got, n), v, (N, F, T) in zip(dump_all(cors), vs, arrays):
         assert n == T

@@ -87,10 +87,11 @@ def test_every_tile_shape_bit_exact(N, tile, variant, monkeypatch):
     assert np.array_equal(got, expected(v, N, F))
 
 
-# tiles 3 and 4 run their triangles two channels to an item: an odd F
+# tiles 2 to 4 run their triangles two channels to an item: an odd F
 # leaves the last item one channel; F = 1 runs single triangles
 PAIRS = [(128, 3, 4), (128, 1, 4), (96, 2, 4), (208, 5, 4), (256, 3, 4), (512, 3, 4),
-         (96, 3, 3), (96, 1, 3), (80, 2, 3), (288, 5, 3), (208, 3, 3)]
+         (96, 3, 3), (96, 1, 3), (80, 2, 3), (288, 5, 3), (208, 3, 3),
+         (64, 3, 2), (64, 1, 2), (48, 2, 2), (320, 3, 2)]
 
 
 @pytest.mark.parametrize("N,F,tile", PAIRS, ids=[f"N{n}F{f}D{d}" for n, f, d in PAIRS])
