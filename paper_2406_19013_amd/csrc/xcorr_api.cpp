@@ -16,7 +16,7 @@
 
 // Kernel family a 4+4-bit int8-MFMA context runs (the tuner times the same).
 enum class Kernel4 {
-    Gauss,   // three products per tile, persistent; whole-triangle regions (default)
+    Gauss,   // three products per tile, persistent; triangles and rectangles (default)
     Fused,   // fused products: one Re and one Im accumulator per tile ($XCORR_MFMA4_VARIANT=fused)
     Roles,   // one wave per real product ($XCORR_MFMA4_VARIANT=roles)
 };
@@ -93,8 +93,9 @@ Kernel4 kernel4_from_env()
     return Kernel4::Gauss;
 }
 
-// The three-product kernel takes plans with one whole-triangle region per
-// channel and N a multiple of 16 (16-byte-aligned inputs are checked per call).
+// The three-product kernel takes every plan it carries (a whole triangle of
+// up to 6 blocks, or segments of up to 4 blocks with the rectangles between
+// them) for N a multiple of 16 (16-byte-aligned inputs are checked per call).
 bool gauss_runs(Kernel4 k, const xc::Plan &pl, int F, int N)
 {
     return k == Kernel4::Gauss && xc::gauss4_supported(pl, F, N);

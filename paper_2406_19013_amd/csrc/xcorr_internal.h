@@ -88,19 +88,22 @@ struct BlockTable {
 hipError_t launch_mfma4f_blocks(const Plan &pl, const BlockTable &bt, int n_blocks, int F, int N, int2 *acc,
                                 int accumulate, hipStream_t s, const int2 *acc_in = nullptr);
 
-// Three-product kernel (4+4-bit, int8 MFMA): persistent, one whole-triangle
-// region per channel (N <= 32 D, D <= 6), N a multiple of 16, 16-byte-aligned
-// input.  acc_in as for launch_mfma4f.
+// Three-product kernel (4+4-bit, int8 MFMA): persistent; a whole triangle per
+// channel (N <= 32 D, D <= 6) or segments of D <= 4 blocks with the rectangles
+// between them (two launches); N a multiple of 16, 16-byte-aligned input.
+// acc_in as for launch_mfma4f.
 bool gauss4_supported(const Plan &pl, int F, int N);
 hipError_t launch_gauss4(const Plan &pl, const uint8_t *volts, int64_t T, int F, int N, int2 *acc, int accumulate,
                          hipStream_t s, const int2 *acc_in = nullptr);
 hipError_t launch_gauss4_blocks(const Plan &pl, const BlockTable &bt, int n_blocks, int F, int N, int2 *acc,
                                 int accumulate, hipStream_t s, const int2 *acc_in = nullptr);
 
-// Batched persistent launch (4+4-bit, int8 MFMA): one kernel drains a work
-// queue of (array, channel, region) items for up to kMaxBatchArrays arrays of
-// uneven N, F and sample counts.  The descriptors travel by value in the
-// kernel arguments, so a captured graph holds everything it needs.
+// Batched launch (4+4-bit, int8 MFMA) over up to kMaxBatchArrays arrays of
+// uneven N, F and sample counts; the descriptors travel by value in the kernel
+// arguments, so a captured graph holds everything it needs.  The queue-driven
+// kernel (launch_batch4) drains a work queue of (array, channel, region)
+// items; the three-product one (launch_gauss4_batch, below) walks per-shape
+// jobs.
 constexpr int kMaxBatchArrays = 16;
 constexpr int kBatchQueueInts = 16;   // 8 per-XCD queue heads, a done counter, padding
 
