@@ -138,6 +138,7 @@ def pin_delay_slope(lib):
     f = np.arange(F)
     slope = np.polyfit(f, phase, 1)[0]                      # rad per channel
     tau_fit = slope / (2 * math.pi * dnu)
+    assert tau_fit != 0, "the phase of V_10 does not vary with frequency"
     vf = gd["cable_difference_m"] / tau_fit / synth.C_LIGHT
     assert abs(vf - gd["velocity_factor"]) <= gd["relative_tolerance"] * gd["velocity_factor"], \
         f"phase slope gives {vf:.4f} c, the paper measured {gd['velocity_factor']} c"
