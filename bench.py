@@ -602,6 +602,26 @@ def main():
     evs2, wall2 = timed(step, mf, 3)
     ingest_ms = np.array([e[0].elapsed_time(e[1]) for e in evs2])
     dump_ms = np.array([e[1].elapsed_time(e[2]) for e in evs2])
+    # an integration over several ingests (Section 2.4: the correlator sums
+    # many blocks before it dumps): the first ingest after a dump stores the
+    # sums, the later ones read and add to them
+    n_acc = 4
+
+    def integration(c, ev=None):
+        for k in range(n_acc):
+            if ev:
+                ev[k].record(stream)
+            c.ingest(volts, T, stream=stream)
+        if ev:
+            ev[n_acc].record(stream)
+        c.dump(out, stream=stream)
+
+    single = out.clone()       # the dump of one ingest (left by the step above)
+    evs3, _ = timed(integration, mf, n_acc + 1)
+    integration_exact = bool(torch.equal(out, single * n_acc))
+    del single
+    store_ms = np.array([e[0].elapsed_time(e[1]) for e in evs3])
+    add_ms = np.array([e[k].elapsed_time(e[k + 1]) for e in evs3 for k in range(1, n_acc)])
 
     # plain VALU path on the same data, same GPU
     plain_ms = float("nan")
@@ -664,6 +684,11 @@ def main():
                        "step_mean": float(step_ms.mean())},
         "separate_calls": {"ms_per_step": wall2 * 1e3 / args.steps, "ingest_mean_ms": float(ingest_ms.mean()),
                            "dump_mean_ms": float(dump_ms.mean())},
+        "integration": {"ingests_per_dump": n_acc, "store_ingest_ms": float(store_ms.mean()),
+                        "accumulate_ingest_ms": float(add_ms.mean()),
+                        "accumulate_hbm_gbs": (in_bytes + 2 * acc_bytes) / (float(add_ms.mean()) / 1e3) / 1e9,
+                        "dump_equals_n_times_one_ingest": integration_exact,
+                        "note": "ingests of 4096 samples each; the later ones also read the running sums"},
         "dump_hbm_gbs": dump_gbs,
         "roofline": {"bound": "mfma", "achieved": achieved_tops, "peak": INT8_PEAK_TOPS,
                      "unit": "TFLOP/s", "frac": achieved_tops / INT8_PEAK_TOPS, "traffic": traffic,

@@ -109,3 +109,24 @@ def test_benchmark_launch_full_size_one_channel_per_xcd_range():
     autos = [oracle.pair_index(i, i) for i in range(N)]
     assert not om[:, autos, 1].any() and (om[:, autos, 0] > 0).all()
     c.close()
+
+
+def test_benchmark_integration_full_size_is_n_times_one_ingest():
+    """An integration of four identical 4096-sample ingests of the benchmark
+    array (192 inputs x 1024 channels; the first stores, the other three add
+    to the running sums) dumps exactly four times what one ingest dumps: a
+    property of the sum that holds on every pair at full size."""
+    N, F, T = 192, 1024, 4096
+    _say("integration at full size: generating")
+    v = synth.tianlai(device="cuda")
+    c = X.Correlator(N, F, 4, X.PATH_I8_MFMA)
+    one = torch.empty((F, N * (N + 1) // 2, 2), dtype=torch.int32, device="cuda")
+    c.ingest_dump(v, one, T)
+    for _ in range(4):
+        c.ingest(v, T)
+    four = torch.empty_like(one)
+    _, n, _ = c.dump(four)
+    torch.cuda.synchronize()
+    assert n == 4 * T
+    assert torch.equal(four, one * 4)
+    c.close()
