@@ -252,6 +252,11 @@ constexpr int g3_mfmas_of(int s)
     return n;
 }
 
+// rows of a tile's running sums that an accumulating epilogue requests ahead
+// of its stores: the whole tile where the registers allow, else half of it
+template <int SH>
+constexpr int g3_old_rows(int D) { return (SH == kTri && D <= 3) || (SH == kPair && D >= 4) ? 8 : 16; }
+
 // LDS transpose slot of a diagonal tile: its block
 template <int D, int SH>
 constexpr int g3_diag_slot(int t) { return g3_row<SH>(D, t); }
@@ -521,6 +526,23 @@ __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const Bl
             const int jloc = J * 32 + jl;
             const int j = (SH == kRect ? cb + (J - D) : rb + Jb) * 32 + jl;
             const int2 ghj = *(const int2 *)&gh[jloc * 2];
+            // running sums of the tile's rows (ACC = 1), OR of them at a time
+            // (the first group before the transpose), each group requested
+            // before the stores it feeds: the elements a thread loads and
+            // stores are its own, so the loads need not wait for earlier
+            // stores (a valid address where the pair does not exist)
+            constexpr int OR = g3_old_rows<SH>(D);
+            int2 old[ACC ? OR : 1];
+            auto load_old = [&](int r0) {
+#pragma unroll
+                for (int r = 0; r < OR; ++r) {
+                    const int i = (rb + Ib) * 32 + 8 * ((r0 + r) >> 2) + il0 + ((r0 + r) & 3);
+                    const bool ok = i < a.N && (!diag || j <= i);
+                    old[r] = in_f[ok ? (int64_t)i * (i + 1) / 2 + j : 0];
+                }
+            };
+            if constexpr (ACC)
+                load_old(0);
             v16i ba;
             if constexpr (diag) {
                 // P_ba of a diagonal tile is the transpose of its P_ab
@@ -538,17 +560,9 @@ __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const Bl
             for (int r4 = 0; r4 < 4; ++r4) {
                 const int ibl = I * 32 + 8 * r4 + il0;                // rows ibl .. ibl + 3 (local)
                 const int ib = (rb + Ib) * 32 + 8 * r4 + il0;         // and their global inputs
-                // running sums of these rows (ACC = 1), from a valid address
-                // where the pair does not exist
-                int2 old[4];
-                if constexpr (ACC) {
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int i = ib + u;
-                        const bool ok = i < a.N && (!diag || j <= i);
-                        old[u] = in_f[ok ? (int64_t)i * (i + 1) / 2 + j : 0];
-                    }
-                }
+                if constexpr (ACC && OR < 16)
+                    if (r4 > 0 && 4 * r4 % OR == 0)
+                        load_old(4 * r4);
                 const int4 ghi01 = *(const int4 *)&gh[ibl * 2];
                 const int4 ghi23 = *(const int4 *)&gh[ibl * 2 + 4];
                 const int gi[4] = {ghi01.x, ghi01.z, ghi23.x, ghi23.z};
@@ -564,8 +578,8 @@ __device__ __forceinline__ void g3_wave(uint8_t *smem, const G3Args &a, const Bl
                     int re = (acc_rr[q][r] >> 8) + ii;
                     int imv = im;
                     if constexpr (ACC) {
-                        re += old[u].x;
-                        imv += old[u].y;
+                        re += old[r % OR].x;
+                        imv += old[r % OR].y;
                     }
                     if (i < a.N && (!diag || j <= i))
                         out_f[(int64_t)i * (i + 1) / 2 + j] = make_int2(re, imv);
