@@ -158,6 +158,22 @@ constexpr int mfma8_smem_bytes(int KC, int D)
                : 4 * mfma8_epilogue_tiles(D) * 4096 + 2 * D * 256;
 }
 
+// Running sums of one quad (rows i0 .. i0+3 of column j, the first at
+// triangle index p), all four requested before any of the quad's stores: a
+// thread loads and stores only its own elements, so the loads need not wait
+// for earlier stores.  A row that does not exist reads element 0 and its
+// value goes unused.
+template <typename T2>
+__device__ __forceinline__ void quad_running_sums(const T2 *dst, int p, int i0, int j, bool diag, int N, T2 (&o)[4])
+{
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const int i = i0 + m;
+        o[m] = dst[i < N && (!diag || j <= i) ? p : 0];
+        p += i + 1;
+    }
+}
+
 template <int D, bool TRI, bool F16, int KC, int NBUF, int VEC, int PROD, int PAR, int HALF>
 __device__ __forceinline__ void mfma8_region(uint8_t *smem, const uint8_t *__restrict__ volts, int64_t T,
                                              int F, int N, int f, int row_blk, int col_blk,
@@ -346,6 +362,9 @@ __device__ __forceinline__ void mfma8_region(uint8_t *smem, const uint8_t *__res
                     const v4f fr0 = __builtin_bit_cast(v4f, re0), fr1 = __builtin_bit_cast(v4f, re1);
                     const v4f fi0 = __builtin_bit_cast(v4f, im0), fi1 = __builtin_bit_cast(v4f, im1);
                     float2 *const dst = static_cast<float2 *>(acc_out) + (int64_t)f * P;
+                    float2 o[4];
+                    if (accumulate)
+                        quad_running_sums(dst, p, i0, j, diag, N, o);
 #pragma unroll
                     for (int m = 0; m < 4; ++m) {
                         const int i = i0 + m;
@@ -353,9 +372,8 @@ __device__ __forceinline__ void mfma8_region(uint8_t *smem, const uint8_t *__res
                             float re = fr0[m] + fr1[m];
                             float im = fi0[m] + fi1[m];
                             if (accumulate) {
-                                const float2 o = dst[p];
-                                re += o.x;
-                                im += o.y;
+                                re += o[m].x;
+                                im += o[m].y;
                             }
                             dst[p] = make_float2(re, im);
                         }
@@ -366,6 +384,9 @@ __device__ __forceinline__ void mfma8_region(uint8_t *smem, const uint8_t *__res
                     const lds_v4i *const rs = (const lds_v4i *)(sstage + I * 64 + il0);
                     const v4i S = rs[0] + rs[8] + rs[D * 16] + rs[D * 16 + 8];
                     int2 *const dst = static_cast<int2 *>(acc_out) + (int64_t)f * P;
+                    int2 o[4];
+                    if (accumulate)
+                        quad_running_sums(dst, p, i0, j, diag, N, o);
 #pragma unroll
                     for (int m = 0; m < 4; ++m) {
                         const int i = i0 + m;
@@ -373,9 +394,8 @@ __device__ __forceinline__ void mfma8_region(uint8_t *smem, const uint8_t *__res
                             int re = re0[m] + re1[m];
                             int im = im0[m] + im1[m] + S[m];
                             if (accumulate) {
-                                const int2 o = dst[p];
-                                re += o.x;
-                                im += o.y;
+                                re += o[m].x;
+                                im += o[m].y;
                             }
                             dst[p] = make_int2(re, im);
                         }

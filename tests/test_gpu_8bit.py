@@ -149,3 +149,26 @@ def test_precision_workload_full_size_sampled():
     assert np.array_equal(outs["int8"][chans].cpu().numpy(), oracle.to_int32(want))
     assert np.array_equal(outs["f16"][chans].cpu().numpy().astype(np.float64), want.astype(np.float64))
     assert torch.equal(outs["int8"], outs["plain"])
+
+
+ACC8 = [(192, 6), (512, 4), (160, 5), (192, 3), (130, 2), (20, 1)]
+
+
+@pytest.mark.parametrize("path", ["int8", "fp16"])
+@pytest.mark.parametrize("N,tile", ACC8, ids=[f"N{n}D{d}" for n, d in ACC8])
+def test_8bit_accumulating_launches_every_tile_shape(path, N, tile):
+    """Several ingests per integration (every launch after the first adds to
+    the running sums) on triangles of 1 to 6 blocks and the rectangles
+    between segments; the FP16 path is exact here (every partial and total
+    sum is an integer below 2^24)."""
+    F, splits = 2, [64, 1, 127]
+    T = sum(splits)
+    _say(f"8bit accumulate {path} N={N} D={tile}")
+    v = synth.gaussian_volts(N, F, T, sigma=20.0, bits=8, seed=(2003, N, tile))
+    got = run(v, N, F, X.PATH_I8_MFMA if path == "int8" else X.PATH_F16_MFMA, tile, splits=splits)
+    want = oracle.xcorr(v.numpy(), 8, T, F, N)
+    assert np.abs(want).max() < 2 ** 24
+    if path == "int8":
+        assert np.array_equal(got, oracle.to_int32(want))
+    else:
+        assert np.array_equal(got.astype(np.float64), want.astype(np.float64))
