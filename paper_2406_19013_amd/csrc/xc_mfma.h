@@ -143,5 +143,23 @@ __device__ __forceinline__ void barrier_no_fence() { asm volatile("s_barrier" ::
 
 constexpr int kMfmaThreads = 512;   // 8 waves per work-group
 
+// Running sums of one quad of an epilogue (rows i0 .. i0+3 of column j of a
+// channel's lower triangle, the first at triangle index p), all four
+// requested before any of the quad's stores: a thread loads and stores only
+// its own elements, so the loads need not wait for earlier stores.  A row
+// that does not exist (past N, or above the diagonal of a diagonal tile)
+// reads element 0 and its value goes unused.
+template <typename T2>
+__device__ __forceinline__ void quad_running_sums(const T2 *sums, int p, int i0, int j, bool diag, int N,
+                                                  T2 (&o)[4])
+{
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const int i = i0 + m;
+        o[m] = sums[i < N && (!diag || j <= i) ? p : 0];
+        p += i + 1;
+    }
+}
+
 }  // namespace
 }  // namespace xc

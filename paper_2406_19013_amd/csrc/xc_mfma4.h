@@ -610,17 +610,18 @@ __device__ __forceinline__ void mfma4f_region(uint8_t *smem, const uint8_t *__re
                 const v4i s0 = rs[0] + rs[8];
                 const v4i s1 = rs[D * 16] + rs[D * 16 + 8];
                 int p = i0 * (i0 + 1) / 2 + j;
+                // the quad's running sums, all requested before its stores
+                int2 oq[4] = {};
+                if constexpr (ACC != 0)
+                    if (ACC == 1 || accumulate)
+                        quad_running_sums(in_f, p, i0, j, true, N, oq);
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
                     const int i = i0 + m;
                     if (i < N && j <= i) {
                         const int re = (re0[m] >> 8) + (re1[m] >> 8);
                         const int im = ((im0[m] + s0[m]) >> 8) + ((im1[m] + s1[m]) >> 8);
-                        int2 o = make_int2(0, 0);
-                        if constexpr (ACC != 0)
-                            if (ACC == 1 || accumulate)
-                                o = in_f[p];
-                        out_f[p] = make_int2(re + o.x, im + o.y);
+                        out_f[p] = make_int2(re + oq[m].x, im + oq[m].y);
                     }
                     p += i + 1;
                 }
@@ -684,18 +685,20 @@ __device__ __forceinline__ void mfma4f_region(uint8_t *smem, const uint8_t *__re
                 const v4i s0 = rs[0] + rs[8];
                 const v4i s1 = rs[D * 16] + rs[D * 16 + 8];
                 int p = i0 * (i0 + 1) / 2 + j;
+                // otherwise the quad's running sums, requested before its stores
+                int2 oq[4] = {};
+                if constexpr (ACC != 0 && !(ACC == 1 && D > 3))
+                    if (ACC == 1 || accumulate)
+                        quad_running_sums(in_f, p, i0, j, diag, N, oq);
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
                     const int i = i0 + m;
                     if (i < N && (!diag || j <= i)) {
                         const int re = (re0[m] >> 8) + (re1[m] >> 8);
                         const int im = ((im0[m] + s0[m]) >> 8) + ((im1[m] + s1[m]) >> 8);
-                        int2 o = make_int2(0, 0);
+                        int2 o = oq[m];
                         if constexpr (ACC == 1 && D > 3)
                             o = old[kc][m];
-                        else if constexpr (ACC != 0)
-                            if (ACC == 1 || accumulate)
-                                o = in_f[p];
                         out_f[p] = make_int2(re + o.x, im + o.y);
                     }
                     p += i + 1;

@@ -158,22 +158,6 @@ constexpr int mfma8_smem_bytes(int KC, int D)
                : 4 * mfma8_epilogue_tiles(D) * 4096 + 2 * D * 256;
 }
 
-// Running sums of one quad (rows i0 .. i0+3 of column j, the first at
-// triangle index p), all four requested before any of the quad's stores: a
-// thread loads and stores only its own elements, so the loads need not wait
-// for earlier stores.  A row that does not exist reads element 0 and its
-// value goes unused.
-template <typename T2>
-__device__ __forceinline__ void quad_running_sums(const T2 *dst, int p, int i0, int j, bool diag, int N, T2 (&o)[4])
-{
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        const int i = i0 + m;
-        o[m] = dst[i < N && (!diag || j <= i) ? p : 0];
-        p += i + 1;
-    }
-}
-
 template <int D, bool TRI, bool F16, int KC, int NBUF, int VEC, int PROD, int PAR, int HALF>
 __device__ __forceinline__ void mfma8_region(uint8_t *smem, const uint8_t *__restrict__ volts, int64_t T,
                                              int F, int N, int f, int row_blk, int col_blk,
